@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the whole hot path -- bin, sub-sample, mesh, normals, labels --
+on one MI355X, for a batch of uneven synthetic sweeps resident in HBM.
+
+One step = the full path over the batch (64 street sweeps; rings drawn from
+{16,32,64,128}, azimuth widths from {1024,2048,4096}; range noise 1 cm; 10%
+dropouts; per-frame seeds).  `value` is points/s of the batched form replayed
+from a captured hipGraph; the same batch is also timed with plain per-frame
+launch chains and with the batched chain launched directly, and the dominant
+kernel is timed with HIP events for the roofline figure.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points/s mesh+normals+labels, batched-served vs plain; p50/p99 frame latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("lidarseg_kernels.hip", "lidarseg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2005_02704_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stage_bytes(stage, N, V, T):
+    """Algorithmic bytes a stage must move (what the method reads and writes,
+    not the key grid or other scratch).  N input points, V vertices, T triangles."""
+    if stage == "bin":
+        return 12 * N                         # xyz of every input point
+    if stage == "tile":
+        return 12 * V + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T  # kept xyz in; vertices,
+        # normals, vertex_point, local labels, triangles out
+    if stage in ("flatten", "rank", "final"):
+        return 8 * V                          # label read + write
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: frames are independent, so a multi-GPU run is one "
+              "single-GPU run per device; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2005_02704_amd as lp
+    import synth
+
+    log(f"generating {args.frames} sweeps (seed {args.seed})")
+    t0 = time.time()
+    frames = synth.batch_frames(args.frames, args.seed)
+    N = sum(f.n_points for f in frames)
+    log(f"  {N} points in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda", 0)
+    ctx = lp.LidarContext(0)
+    params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2))
+    geos = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, 1, 1, f.sensor.az0) for f in frames]
+    inputs = [(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)]
+    outs = [lp.Outputs(g, dev) for g in geos]
+    prep = ctx.prepare(inputs, params, outs)
+    stream = torch.cuda.current_stream(dev)
+
+    def run(launch, steps, warmup):
+        for _ in range(warmup):
+            ctx.lidar_mesh_segment(prep, stream, launch)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.lidar_mesh_segment(prep, stream, launch)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1000.0 / steps
+
+    log("timing graph replays")
+    ms_graph = run("graph", args.steps, args.warmup)
+    counts = np.array([[int(x) for x in o.counts.cpu()] for o in outs])
+    V, T = int(counts[:, 0].sum()), int(counts[:, 1].sum())
+    log(f"  graph: {ms_graph:.3f} ms/step  V={V} T={T}")
+    log("timing batched launches")
+    ms_batched = run("batched", args.steps, args.warmup)
+    log(f"  batched: {ms_batched:.3f} ms/step")
+    log("timing plain per-frame chains")
+    ms_plain = run("plain", args.steps, args.warmup)
+    log(f"  plain: {ms_plain:.3f} ms/step")
+
+    # dominant kernel: per-stage HIP events on the launch stream over K batched steps
+    log("timing stages with HIP events")
+    ctx.stage_times()
+    ctx.set_profiling(True)
+    for _ in range(args.steps):
+        ctx.lidar_mesh_segment(prep, stream, "batched")
+    torch.cuda.synchronize()
+    st = ctx.stage_times()
+    ctx.set_profiling(False)
+    per_launch = {k: ms / n for k, (ms, n) in st.items() if n}
+    dom = max(per_launch, key=per_launch.get)
+    dom_ms = per_launch[dom]
+    dom_bytes = stage_bytes(dom, N, V, T)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    log("  stages (ms/launch): " + ", ".join(f"{k} {v:.4f}" for k, v in per_launch.items()))
+
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_k_{dom}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("frames") == args.frames \
+                and tr.get("seed") == args.seed:
+            traffic = tr.get("hbm_bytes_per_launch")
+
+    roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 5),
+                "stage_ms": {k: round(v, 5) for k, v in per_launch.items()}}
+    alg_path = 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T
+    path_gbs = alg_path / (ms_graph * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log(f"timing the oracle on the host for ~{args.cpu_seconds:.0f}s")
+        done_pts, n_fr = 0, 0
+        t = time.perf_counter()
+        for f in frames:
+            oracle.mesh_segment_frame(f)
+            done_pts += f.n_points
+            n_fr += 1
+            if time.perf_counter() - t > args.cpu_seconds:
+                break
+        el = time.perf_counter() - t
+        cpu = {"value": round(done_pts / el, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n_fr} of the {args.frames} sweeps ({done_pts} points), single thread, "
+                         f"host has {os.cpu_count()} CPUs"}
+        log(f"  oracle: {done_pts / el:.0f} points/s")
+
+    value = N / (ms_graph * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_graph, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched {args.frames} uneven street sweeps (rings 16/32/64/128, "
+                               f"azimuth 1024/2048/4096, s=1)", "frames": args.frames,
+                   "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
+                   "launch": "graph", "seed": args.seed},
+        "forms": {
+            "graph": {"points_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4)},
+            "batched": {"points_per_s": round(N / (ms_batched * 1e-3), 1), "ms_per_step": round(ms_batched, 4)},
+            "plain": {"points_per_s": round(N / (ms_plain * 1e-3), 1), "ms_per_step": round(ms_plain, 4)},
+        },
+        "path_algorithmic_gbs": round(path_gbs, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

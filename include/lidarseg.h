@@ -1,0 +1,142 @@
+/*
+ * lidarseg.h -- C ABI of the MI355X (gfx950) Lidar mesh-and-segment library.
+ *
+ * One spinning-Lidar sweep P = {p(theta, phi, r)} (Mukherjee et al., PReMI 2019,
+ * Section 2, opening paragraph) is turned into
+ *   - the vertices of its sub-sampled (ring x azimuth) lattice,
+ *   - the mesh triangles joining lattice neighbours      (Section 2, Mesh Construction),
+ *   - one normal per vertex                              (Section 2, Normal Estimation),
+ *   - one surface label per vertex                       (Section 2, Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *   - All data pointers named "device" are HIP device memory owned by the caller;
+ *     they must stay valid until the work enqueued on `stream` has finished.
+ *   - Calls are asynchronous: they validate arguments on the host, enqueue work on
+ *     `stream` (a hipStream_t; NULL = the default stream) and return.
+ *   - Return codes: LIDAR_OK (0) or a negative LIDAR_E* code; the message of the
+ *     last failure is available from lidar_ctx_last_error().  Argument errors are
+ *     reported before anything is enqueued.
+ *   - A context is used by one host thread at a time; contexts are independent and
+ *     may run concurrently on different streams.
+ *
+ * Lattice conventions (see also the readings in the repository's design notes)
+ *   - Ring i = 0 is the topmost laser, counting downwards; elevations are given
+ *     strictly descending.  Azimuth phi = atan2(y, x) (anticlockwise about +z);
+ *     firing j has phi_j = az0 + j * 2*pi / W.  A point belongs to the ring of
+ *     nearest elevation (tie: lower i) and to firing round((phi - az0)/dphi) mod W
+ *     (round half away from zero); both decided in FP64.
+ *   - Sub-sampling keeps firings j = 0 (mod s); sampled column k = j / s, W' = W / s.
+ *   - A point is used iff its coordinates are finite and
+ *     r_min^2 <= x^2 + y^2 + z^2 <= r_max^2 (FP64).  Two points in one cell: the
+ *     smaller float(r^2) wins, then the lower input index.
+ *   - Vertices are the occupied cells, numbered in firing order: column-major,
+ *     (k, i) lexicographic.  Labels 1..K are numbered by each segment's first
+ *     vertex in that order.
+ */
+#ifndef LIDARSEG_H
+#define LIDARSEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LIDAR_OK 0
+#define LIDAR_EINVAL (-1)   /* bad argument; nothing was enqueued */
+#define LIDAR_ENOMEM (-2)   /* device workspace could not be allocated */
+#define LIDAR_EDEVICE (-3)  /* a HIP runtime call failed */
+
+#define LIDAR_MAX_RINGS 128
+
+/* Launch forms of lidar_mesh_segment. */
+#define LIDAR_LAUNCH_PLAIN 0    /* each frame on its own: one kernel chain per frame */
+#define LIDAR_LAUNCH_BATCHED 1  /* all frames together: one grid-stride launch per stage */
+#define LIDAR_LAUNCH_GRAPH 2    /* the batched chain replayed from a captured hipGraph */
+
+typedef struct lidar_ctx lidar_ctx;
+
+/* Sensor geometry (Section 2, Mesh Construction: rings theta_0..theta_n from the
+ * top, firings phi_0..phi_m from the first shot of the spin). */
+typedef struct {
+    int32_t n_rings;         /* H, 1..LIDAR_MAX_RINGS */
+    int32_t n_azimuth;       /* W, firings per spin, >= 1 */
+    int32_t subsample;       /* s >= 1, W % s == 0 (the paper's sampling interval) */
+    int32_t wrap;            /* 1: join column W'-1 to column 0 (closed cylinder); 0: open */
+    const double* elev_rad;  /* host, H ring elevations in radians, strictly descending */
+    double az0_rad;          /* azimuth of firing 0 */
+} lidar_sensor_t;
+
+/* One sweep. */
+typedef struct {
+    const lidar_sensor_t* sensor;  /* host */
+    const float* xyz;              /* device, [n_points][3] FP32, any order */
+    int64_t n_points;              /* 0 .. 2^31-1 */
+    const float* normals_in;       /* device [V][3] or NULL.  When given, the normal
+                                      stage is skipped and these per-vertex normals
+                                      (zero vector = no normal) are labelled instead;
+                                      V must be this frame's vertex count. */
+} lidar_frame_t;
+
+/* Parameters (Section 2, Mesh Construction "within range of the Lidar";
+ * Algorithm 1 thresholds I, J, K, which Section 3 sets to 0.2 each). */
+typedef struct {
+    double r_min, r_max;  /* valid range window in metres, 0 <= r_min <= r_max */
+    double thr[3];        /* I, J, K > 0: a neighbour joins when every component of
+                             the normal differs by strictly less (exact FP64 difference
+                             of the FP32 normals) */
+} lidar_params_t;
+
+/* Caller-owned outputs of one frame, sized by lidar_query_sizes().  Written
+ * compactly from index 0; counts tells how many entries are valid. */
+typedef struct {
+    float* vertices;        /* device [V][3]: the kept input points, bit-exact */
+    float* normals;         /* device [V][3]: unit normals, zero vector = no normal */
+    int32_t* labels;        /* device [V]: 1..K.  Also used as scratch while labelling */
+    int32_t* triangles;     /* device [T][3]: vertex indices, each oriented so that
+                               (v1-v0) x (v2-v0) points away from the sensor */
+    int32_t* vertex_point;  /* device [V] or NULL: input index of each vertex */
+    int64_t* counts;        /* device [3]: V, T, K */
+} lidar_result_t;
+
+/* Create a context on HIP device `device`.  The context owns its device
+ * workspace (grown on demand) and any captured graph. */
+int lidar_ctx_create(int device, lidar_ctx** out);
+void lidar_ctx_destroy(lidar_ctx* ctx);
+/* Message of the last failed call on this context ("" if none).  Owned by ctx. */
+const char* lidar_ctx_last_error(const lidar_ctx* ctx);
+/* Message of the last failure outside any context (creation, size queries). */
+const char* lidar_last_error(void);
+
+/* Output capacities for one frame of this sensor: V <= H*W', T <= 2*(H-1)*W'. */
+int lidar_query_sizes(const lidar_sensor_t* sensor, int64_t* max_vertices,
+                      int64_t* max_triangles);
+
+/* Bin, sub-sample, mesh, estimate normals and label n_frames sweeps
+ * (Section 2 in full; Algorithm 1 is computed as the connected components of
+ * the similar-join graph, which is the partition it produces).
+ * launch: LIDAR_LAUNCH_PLAIN, _BATCHED or _GRAPH.  results has n_frames entries. */
+int lidar_mesh_segment(lidar_ctx* ctx, const lidar_frame_t* frames, int32_t n_frames,
+                       const lidar_params_t* params, lidar_result_t* results,
+                       void* stream, int32_t launch);
+
+/* Tuning of the batched forms: workgroups per stage launch (0 = automatic) and
+ * the largest tile in lattice cells (512, 1024 or 2048; 0 = automatic). */
+int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_cells);
+
+/* Per-stage timing of plain and batched launches (not of graph replays), with
+ * HIP events recorded on the launch stream around each kernel of the chain.
+ * Stages, in order: bin, count, scan, tile (mesh + normals + local segments),
+ * merge, flatten, scan roots, rank, final.  Enabling costs one event per kernel. */
+#define LIDAR_N_STAGES 9
+int lidar_ctx_set_profiling(lidar_ctx* ctx, int32_t enable);
+/* Waits for the profiled calls, then writes the summed milliseconds and the
+ * number of timed launches of each stage (arrays of LIDAR_N_STAGES; launches
+ * may be NULL) and resets the accumulators. */
+int lidar_ctx_stage_times(lidar_ctx* ctx, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIDARSEG_H */

@@ -1,0 +1,513 @@
+// Host side of liblidarseg: argument validation, workspace planning, descriptor
+// tables, launch forms (plain per-frame chains, one batched chain, or a captured
+// hipGraph of the batched chain).  The C ABI is declared in include/lidarseg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lidarseg.h"
+#include "lidarseg_internal.h"
+
+using namespace lidarseg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct lidar_ctx {
+    int device = 0;
+    int cu_count = 256;
+    std::string err;
+
+    // device workspace
+    uint64_t* keys = nullptr;
+    int64_t keys_cap = 0;
+    int32_t* tile_buf = nullptr;  // 6 arrays of tiles_cap
+    int64_t tiles_cap = 0;
+    int2* border = nullptr;
+    int64_t border_cap = 0;
+    char* d_table = nullptr;      // descriptor tables + elevations
+    char* h_table[2] = {nullptr, nullptr};  // pinned staging of d_table, used alternately
+    size_t table_cap = 0;
+    hipEvent_t done[2] = {nullptr, nullptr};  // end of the call that last used h_table[b]
+    bool pending[2] = {false, false};
+    int flip = 0;
+
+    // captured batched chain
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_valid = false;
+    size_t graph_table_bytes = 0;
+    int graph_tiles_cap = 0, graph_pblk_cap = 0, graph_frames_cap = 0;
+    int graph_tile_cells = 0;
+
+    // tuning
+    int grid_wg = 0;      // 0 = automatic
+    int tile_cells = 1024;
+
+    // per-stage timing
+    bool profiling = false;
+    std::vector<std::vector<hipEvent_t>> prof_sets;  // one set of N_STAGES+1 events per chain
+    std::vector<hipEvent_t> prof_free;
+    double prof_ms[N_STAGES] = {0};
+    int64_t prof_n[N_STAGES] = {0};
+
+    hipEvent_t* new_event_set() {
+        std::vector<hipEvent_t> set(N_STAGES + 1);
+        for (auto& ev : set) {
+            if (!prof_free.empty()) {
+                ev = prof_free.back();
+                prof_free.pop_back();
+            } else if (hipEventCreate(&ev) != hipSuccess) {
+                return nullptr;
+            }
+        }
+        prof_sets.push_back(std::move(set));
+        return prof_sets.back().data();
+    }
+
+    int fail(int code, const std::string& msg) {
+        err = msg;
+        g_last_error = msg;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* what) {
+        return fail(LIDAR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    Workspace workspace() const {
+        Workspace ws;
+        ws.keys = keys;
+        ws.tile_v = tile_buf;
+        ws.tile_t = tile_buf + tiles_cap;
+        ws.tile_vbase = tile_buf + 2 * tiles_cap;
+        ws.tile_tbase = tile_buf + 3 * tiles_cap;
+        ws.tile_r = tile_buf + 4 * tiles_cap;
+        ws.tile_rbase = tile_buf + 5 * tiles_cap;
+        ws.border = border;
+        ws.elev = reinterpret_cast<const double*>(d_table);
+        return ws;
+    }
+    void drop_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        graph_valid = false;
+    }
+    int wait_buffer(int b) {
+        if (pending[b]) {
+            hipError_t e = hipEventSynchronize(done[b]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            pending[b] = false;
+        }
+        return LIDAR_OK;
+    }
+    int wait_idle() {
+        int rc = wait_buffer(0);
+        return rc ? rc : wait_buffer(1);
+    }
+};
+
+namespace {
+
+struct FramePlan {
+    int H, W, s, Wp, wrap, TW, n_tiles, n_pblk;
+    int64_t cells, border_slots;
+};
+
+int validate_sensor(const lidar_sensor_t* sen, std::string& msg) {
+    if (!sen) { msg = "sensor is NULL"; return LIDAR_EINVAL; }
+    const int H = sen->n_rings, W = sen->n_azimuth, s = sen->subsample;
+    if (H < 1 || H > LIDAR_MAX_RINGS) { msg = "n_rings must be in [1, 128]"; return LIDAR_EINVAL; }
+    if (W < 1) { msg = "n_azimuth must be >= 1"; return LIDAR_EINVAL; }
+    if (s < 1 || W % s != 0) { msg = "subsample must be >= 1 and divide n_azimuth"; return LIDAR_EINVAL; }
+    if (sen->wrap != 0 && sen->wrap != 1) { msg = "wrap must be 0 or 1"; return LIDAR_EINVAL; }
+    if (sen->wrap && W / s < 3) { msg = "a closed cylinder needs at least 3 sampled columns"; return LIDAR_EINVAL; }
+    if ((int64_t)H * (W / s) > (int64_t)1 << 30) { msg = "lattice too large"; return LIDAR_EINVAL; }
+    if (!sen->elev_rad) { msg = "elev_rad is NULL"; return LIDAR_EINVAL; }
+    for (int i = 0; i < H; ++i) {
+        if (!std::isfinite(sen->elev_rad[i])) { msg = "elevations must be finite"; return LIDAR_EINVAL; }
+        if (i > 0 && !(sen->elev_rad[i] < sen->elev_rad[i - 1])) {
+            msg = "elevations must be strictly descending (ring 0 = top)";
+            return LIDAR_EINVAL;
+        }
+    }
+    if (!std::isfinite(sen->az0_rad)) { msg = "az0_rad must be finite"; return LIDAR_EINVAL; }
+    return LIDAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lidar_last_error(void) { return g_last_error.c_str(); }
+
+const char* lidar_ctx_last_error(const lidar_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int lidar_query_sizes(const lidar_sensor_t* sensor, int64_t* max_vertices, int64_t* max_triangles) {
+    std::string msg;
+    int rc = validate_sensor(sensor, msg);
+    if (rc) { g_last_error = msg; return rc; }
+    const int64_t Wp = sensor->n_azimuth / sensor->subsample;
+    if (max_vertices) *max_vertices = (int64_t)sensor->n_rings * Wp;
+    if (max_triangles) *max_triangles = 2 * (int64_t)(sensor->n_rings - 1) * Wp;
+    return LIDAR_OK;
+}
+
+int lidar_ctx_create(int device, lidar_ctx** out) {
+    if (!out) { g_last_error = "out is NULL"; return LIDAR_EINVAL; }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n) {
+        g_last_error = "no such HIP device";
+        return LIDAR_EINVAL;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) { g_last_error = hipGetErrorString(e); return LIDAR_EDEVICE; }
+    lidar_ctx* c = new lidar_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->cu_count = prop.multiProcessorCount;
+    for (int b = 0; b < 2; ++b) {
+        e = hipEventCreateWithFlags(&c->done[b], hipEventDisableTiming);
+        if (e != hipSuccess) { g_last_error = hipGetErrorString(e); lidar_ctx_destroy(c); return LIDAR_EDEVICE; }
+    }
+    *out = c;
+    return LIDAR_OK;
+}
+
+void lidar_ctx_destroy(lidar_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    c->wait_idle();
+    c->drop_graph();
+    for (auto& set : c->prof_sets)
+        for (auto ev : set) (void)hipEventDestroy(ev);
+    for (auto ev : c->prof_free) (void)hipEventDestroy(ev);
+    if (c->keys) (void)hipFree(c->keys);
+    if (c->tile_buf) (void)hipFree(c->tile_buf);
+    if (c->border) (void)hipFree(c->border);
+    if (c->d_table) (void)hipFree(c->d_table);
+    for (int b = 0; b < 2; ++b) {
+        if (c->h_table[b]) (void)hipHostFree(c->h_table[b]);
+        if (c->done[b]) (void)hipEventDestroy(c->done[b]);
+    }
+    delete c;
+}
+
+int lidar_ctx_set_tuning(lidar_ctx* c, int32_t grid_workgroups, int32_t tile_cells) {
+    if (!c) return LIDAR_EINVAL;
+    if (grid_workgroups < 0) return c->fail(LIDAR_EINVAL, "grid_workgroups must be >= 0");
+    if (tile_cells != 0 && tile_cells != 512 && tile_cells != 1024 && tile_cells != 2048)
+        return c->fail(LIDAR_EINVAL, "tile_cells must be 0, 512, 1024 or 2048");
+    c->grid_wg = grid_workgroups;
+    c->tile_cells = tile_cells ? tile_cells : 1024;
+    c->drop_graph();
+    return LIDAR_OK;
+}
+
+int lidar_ctx_set_profiling(lidar_ctx* c, int32_t enable) {
+    if (!c) return LIDAR_EINVAL;
+    c->profiling = enable != 0;
+    return LIDAR_OK;
+}
+
+int lidar_ctx_stage_times(lidar_ctx* c, double* total_ms, int64_t* launches) {
+    if (!c || !total_ms) return LIDAR_EINVAL;
+    for (auto& set : c->prof_sets) {
+        hipError_t e = hipEventSynchronize(set[N_STAGES]);
+        if (e != hipSuccess) return c->hip_fail(e, "hipEventSynchronize");
+        for (int k = 0; k < N_STAGES; ++k) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, set[k], set[k + 1]);
+            if (e != hipSuccess) return c->hip_fail(e, "hipEventElapsedTime");
+            c->prof_ms[k] += ms;
+            c->prof_n[k] += 1;
+        }
+        for (auto ev : set) c->prof_free.push_back(ev);
+    }
+    c->prof_sets.clear();
+    for (int k = 0; k < N_STAGES; ++k) {
+        total_ms[k] = c->prof_ms[k];
+        if (launches) launches[k] = c->prof_n[k];
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    return LIDAR_OK;
+}
+
+int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
+                       const lidar_params_t* params, lidar_result_t* results, void* stream_,
+                       int32_t launch) {
+    if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    if (n_frames < 1 || !frames || !results) return c->fail(LIDAR_EINVAL, "need n_frames >= 1 frames and results");
+    if (!params) return c->fail(LIDAR_EINVAL, "params is NULL");
+    if (launch != LIDAR_LAUNCH_PLAIN && launch != LIDAR_LAUNCH_BATCHED && launch != LIDAR_LAUNCH_GRAPH)
+        return c->fail(LIDAR_EINVAL, "unknown launch form");
+    const double rmin = params->r_min, rmax = params->r_max;
+    if (!(std::isfinite(rmin) && std::isfinite(rmax) && rmin >= 0.0 && rmin <= rmax))
+        return c->fail(LIDAR_EINVAL, "need finite 0 <= r_min <= r_max");
+    for (int q = 0; q < 3; ++q)
+        if (!(std::isfinite(params->thr[q]) && params->thr[q] > 0.0))
+            return c->fail(LIDAR_EINVAL, "thresholds must be finite and > 0");
+
+    // ---- plan ----
+    std::vector<FramePlan> plan(n_frames);
+    int64_t cells = 0, border_slots = 0, elev_total = 0;
+    int64_t tiles = 0, pblk = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const lidar_frame_t& fr = frames[f];
+        std::string msg;
+        int rc = validate_sensor(fr.sensor, msg);
+        if (rc) return c->fail(rc, "frame " + std::to_string(f) + ": " + msg);
+        if (fr.n_points < 0 || fr.n_points > INT32_MAX)
+            return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": n_points out of range");
+        if (fr.n_points > 0 && !fr.xyz)
+            return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": xyz is NULL");
+        const lidar_result_t& r = results[f];
+        if (!r.vertices || !r.normals || !r.labels || !r.triangles || !r.counts)
+            return c->fail(LIDAR_EINVAL, "result " + std::to_string(f) + ": a required output is NULL");
+        FramePlan& p = plan[f];
+        p.H = fr.sensor->n_rings;
+        p.W = fr.sensor->n_azimuth;
+        p.s = fr.sensor->subsample;
+        p.Wp = p.W / p.s;
+        p.wrap = fr.sensor->wrap;
+        p.TW = tile_width(p.H, c->tile_cells);
+        p.n_tiles = (p.Wp + p.TW - 1) / p.TW;
+        p.n_pblk = (int)((fr.n_points + POINT_BLOCK - 1) / POINT_BLOCK);
+        p.cells = (int64_t)p.H * p.Wp;
+        p.border_slots = (int64_t)p.n_tiles * 2 * p.H;
+        cells += p.cells;
+        border_slots += p.border_slots;
+        elev_total += p.H;
+        tiles += p.n_tiles;
+        pblk += p.n_pblk;
+    }
+    if (tiles > INT32_MAX || pblk > INT32_MAX) return c->fail(LIDAR_EINVAL, "batch too large");
+
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+
+    // table bytes: batched = one header, all descs, elevations; plain = one
+    // (header, desc, elevations) group per frame.
+    const size_t desc_bytes = sizeof(FrameDesc);
+    size_t table_bytes;
+    if (launch == LIDAR_LAUNCH_PLAIN) {
+        table_bytes = 0;
+        for (int f = 0; f < n_frames; ++f)
+            table_bytes += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
+    } else {
+        table_bytes = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) + 8 * (size_t)elev_total;
+    }
+
+    // ---- capacity ----
+    const bool grow = cells > c->keys_cap || tiles > c->tiles_cap || border_slots > c->border_cap ||
+                      table_bytes > c->table_cap;
+    if (grow) {
+        int rc = c->wait_idle();
+        if (rc) return rc;
+        (void)hipDeviceSynchronize();
+        c->drop_graph();
+        if (cells > c->keys_cap) {
+            if (c->keys) (void)hipFree(c->keys);
+            c->keys = nullptr;
+            const int64_t cap = std::max<int64_t>(cells, c->keys_cap * 3 / 2);
+            if (hipMalloc(&c->keys, sizeof(uint64_t) * cap) != hipSuccess) {
+                c->keys_cap = 0;
+                return c->fail(LIDAR_ENOMEM, "cannot allocate the key grid");
+            }
+            // every chain resets the cells it used, so this fill happens once
+            e = hipMemsetAsync(c->keys, 0xFF, sizeof(uint64_t) * cap, stream);
+            if (e != hipSuccess) return c->hip_fail(e, "hipMemsetAsync");
+            c->keys_cap = cap;
+        }
+        if (tiles > c->tiles_cap) {
+            if (c->tile_buf) (void)hipFree(c->tile_buf);
+            c->tile_buf = nullptr;
+            const int64_t cap = std::max<int64_t>(tiles, c->tiles_cap * 3 / 2);
+            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 6 * cap) != hipSuccess) {
+                c->tiles_cap = 0;
+                return c->fail(LIDAR_ENOMEM, "cannot allocate tile arrays");
+            }
+            c->tiles_cap = cap;
+        }
+        if (border_slots > c->border_cap) {
+            if (c->border) (void)hipFree(c->border);
+            c->border = nullptr;
+            const int64_t cap = std::max<int64_t>(border_slots, c->border_cap * 3 / 2);
+            if (hipMalloc(&c->border, sizeof(int2) * cap) != hipSuccess) {
+                c->border_cap = 0;
+                return c->fail(LIDAR_ENOMEM, "cannot allocate border slots");
+            }
+            c->border_cap = cap;
+        }
+        if (table_bytes > c->table_cap) {
+            if (c->d_table) (void)hipFree(c->d_table);
+            c->d_table = nullptr;
+            for (int b = 0; b < 2; ++b) {
+                if (c->h_table[b]) (void)hipHostFree(c->h_table[b]);
+                c->h_table[b] = nullptr;
+            }
+            const size_t cap = align_up(std::max(table_bytes, c->table_cap * 3 / 2), 4096);
+            if (hipMalloc(&c->d_table, cap) != hipSuccess ||
+                hipHostMalloc(&c->h_table[0], cap, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc(&c->h_table[1], cap, hipHostMallocDefault) != hipSuccess) {
+                c->table_cap = 0;
+                return c->fail(LIDAR_ENOMEM, "cannot allocate descriptor tables");
+            }
+            c->table_cap = cap;
+        }
+    }
+
+    // ---- fill a pinned table (after the call that used it last has finished) ----
+    const int buf = c->flip;
+    {
+        int rc = c->wait_buffer(buf);
+        if (rc) return rc;
+    }
+    char* const htab = c->h_table[buf];
+    std::memset(htab, 0, table_bytes);
+    auto fill_desc = [&](FrameDesc& d, int f, int64_t cell_off, int64_t border_off, int tile_off,
+                         int pblk_off, int elev_off) {
+        const lidar_frame_t& fr = frames[f];
+        const lidar_result_t& r = results[f];
+        const FramePlan& p = plan[f];
+        d.xyz = fr.xyz;
+        d.normals_in = fr.normals_in;
+        d.vertices = r.vertices;
+        d.normals = r.normals;
+        d.labels = r.labels;
+        d.tris = r.triangles;
+        d.vpoint = r.vertex_point;
+        d.counts = r.counts;
+        d.n_points = fr.n_points;
+        d.cell_off = cell_off;
+        d.border_off = border_off;
+        d.H = p.H; d.W = p.W; d.s = p.s; d.Wp = p.Wp; d.wrap = p.wrap; d.TW = p.TW;
+        d.n_tiles = p.n_tiles; d.tile_off = tile_off;
+        d.n_pblk = p.n_pblk; d.pblk_off = pblk_off;
+        d.elev_off = elev_off;
+        d.az0 = fr.sensor->az0_rad;
+        d.dphi = 2.0 * M_PI / (double)p.W;
+        d.rmin2 = rmin * rmin;
+        d.rmax2 = rmax * rmax;
+        d.thr[0] = params->thr[0]; d.thr[1] = params->thr[1]; d.thr[2] = params->thr[2];
+        std::memcpy(htab + 8 * (size_t)elev_off, fr.sensor->elev_rad, 8 * (size_t)p.H);
+    };
+
+    Workspace ws = c->workspace();
+    const int auto_grid = c->grid_wg > 0 ? c->grid_wg : 4 * c->cu_count;
+
+    if (launch == LIDAR_LAUNCH_PLAIN) {
+        std::vector<size_t> offs(n_frames);
+        size_t off = 0;
+        for (int f = 0; f < n_frames; ++f) {
+            offs[f] = off;
+            BatchHeader* h = reinterpret_cast<BatchHeader*>(htab + off);
+            h->n_frames = 1;
+            h->total_tiles = plan[f].n_tiles;
+            h->total_pblk = plan[f].n_pblk;
+            FrameDesc* d = h->frames();
+            const size_t elev_byte = off + sizeof(BatchHeader) + desc_bytes;
+            // frames run one after another on the stream, so they share workspace offsets
+            fill_desc(*d, f, 0, 0, 0, 0, (int)(elev_byte / 8));
+            off += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
+        }
+        e = hipMemcpyAsync(c->d_table, htab, table_bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync");
+        for (int f = 0; f < n_frames; ++f) {
+            LaunchCfg cfg;
+            cfg.tile_cells = c->tile_cells;
+            cfg.max_tiles = plan[f].n_tiles;
+            cfg.max_pblk = plan[f].n_pblk;
+            cfg.max_frames = 1;
+            cfg.grid = std::max(plan[f].n_tiles, plan[f].n_pblk);
+            hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
+            e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table + offs[f]), ws, cfg, stream, ev);
+            if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
+        }
+    } else {
+        BatchHeader* h = reinterpret_cast<BatchHeader*>(htab);
+        h->n_frames = n_frames;
+        h->total_tiles = (int)tiles;
+        h->total_pblk = (int)pblk;
+        FrameDesc* d = h->frames();
+        const size_t elev_base = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) / 8;
+        int64_t cell_off = 0, border_off = 0;
+        int tile_off = 0, pblk_off = 0, elev_off = (int)elev_base;
+        for (int f = 0; f < n_frames; ++f) {
+            fill_desc(d[f], f, cell_off, border_off, tile_off, pblk_off, elev_off);
+            cell_off += plan[f].cells;
+            border_off += plan[f].border_slots;
+            tile_off += plan[f].n_tiles;
+            pblk_off += plan[f].n_pblk;
+            elev_off += plan[f].H;
+        }
+        // the device table is read only by this call's kernels, which run after
+        // this copy in stream order; the next call's copy follows them likewise
+        e = hipMemcpyAsync(c->d_table, htab, table_bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync");
+        if (launch == LIDAR_LAUNCH_BATCHED) {
+            LaunchCfg cfg;
+            cfg.tile_cells = c->tile_cells;
+            cfg.max_tiles = (int)tiles;
+            cfg.max_pblk = (int)pblk;
+            cfg.max_frames = n_frames;
+            cfg.grid = auto_grid;
+            hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
+            e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
+            if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
+        } else {
+            // The captured chain uses fixed grid-stride grids and reads the batch
+            // from the device table, so it serves every batch that fits the workspace.
+            if (!c->graph_valid || c->graph_table_bytes != c->table_cap ||
+                c->graph_tile_cells != c->tile_cells) {
+                c->drop_graph();
+                hipStream_t cap_stream;
+                e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) return c->hip_fail(e, "hipStreamCreate");
+                e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) { hipStreamDestroy(cap_stream); return c->hip_fail(e, "hipStreamBeginCapture"); }
+                LaunchCfg cfg;
+                cfg.tile_cells = c->tile_cells;
+                cfg.max_tiles = (int)std::min<int64_t>(c->tiles_cap, INT32_MAX);
+                cfg.max_pblk = INT32_MAX;
+                cfg.max_frames = 1024;
+                cfg.grid = auto_grid;
+                hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
+                e = hipStreamEndCapture(cap_stream, &c->graph);
+                (void)hipStreamDestroy(cap_stream);
+                if (e2 != hipSuccess) return c->hip_fail(e2, "capture launch");
+                if (e != hipSuccess) return c->hip_fail(e, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) { c->drop_graph(); return c->hip_fail(e, "hipGraphInstantiate"); }
+                c->graph_valid = true;
+                c->graph_table_bytes = c->table_cap;
+                c->graph_tile_cells = c->tile_cells;
+            }
+            e = hipGraphLaunch(c->graph_exec, stream);
+            if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
+        }
+    }
+    e = hipEventRecord(c->done[buf], stream);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+    c->pending[buf] = true;
+    c->flip ^= 1;
+    c->err.clear();
+    return LIDAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal layout shared by the host part and the kernels of liblidarseg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lidarseg {
+
+constexpr uint64_t KEY_EMPTY = ~0ull;
+constexpr int MAX_RINGS = 128;
+constexpr int POINT_BLOCK = 2048;  // points per binning work item
+
+// One frame of a batch, as the kernels see it.  Lives in device memory right
+// after a BatchHeader; all offsets index the context's workspace arrays.
+struct FrameDesc {
+    const float* xyz;         // [n_points][3]
+    const float* normals_in;  // optional per-vertex normals to label instead
+    float* vertices;
+    float* normals;
+    int32_t* labels;
+    int32_t* tris;
+    int32_t* vpoint;          // may be null
+    int64_t* counts;
+    int64_t n_points;
+    int64_t cell_off;         // first cell of this frame in the key grid
+    int64_t border_off;       // first border slot (int2) of this frame
+    int32_t H, W, s, Wp, wrap, TW;
+    int32_t n_tiles, tile_off;
+    int32_t n_pblk, pblk_off;
+    int32_t elev_off, pad0;
+    double az0, dphi, rmin2, rmax2;
+    double thr[3];
+};
+
+struct BatchHeader {
+    int32_t n_frames;
+    int32_t total_tiles;
+    int32_t total_pblk;
+    int32_t pad;
+    FrameDesc* frames() { return reinterpret_cast<FrameDesc*>(this + 1); }
+};
+static_assert(sizeof(BatchHeader) == 16, "header size");
+static_assert(sizeof(FrameDesc) % 8 == 0, "desc alignment");
+
+// Device workspace of a context.  Per-tile arrays are indexed by the batch-wide
+// tile index; keys by cell_off + k*H + i (firing order within a frame).
+struct Workspace {
+    uint64_t* keys;       // (float(r^2) bits << 32) | point index; KEY_EMPTY = no point
+    int32_t* tile_v;      // vertices owned by the tile
+    int32_t* tile_t;      // triangles anchored in the tile
+    int32_t* tile_vbase;  // first vertex index of the tile (frame-local)
+    int32_t* tile_tbase;  // first triangle index of the tile
+    int32_t* tile_r;      // segment roots owned by the tile
+    int32_t* tile_rbase;  // rank of the tile's first root
+    int2* border;         // similar joins leaving a tile through its right edge
+    const double* elev;   // ring elevations, per frame at elev_off
+};
+
+// Tile geometry: a tile is TW consecutive sampled columns, all H rings.
+inline int tile_width(int H, int tile_cells) {
+    int tw = tile_cells / H;
+    return tw < 1 ? 1 : tw;
+}
+
+// kernels (lidarseg_kernels.hip)
+struct LaunchCfg {
+    int grid;        // workgroups for grid-stride stages (tiles / point blocks)
+    int tile_cells;  // 512, 1024 or 2048
+    int max_tiles;   // tiles in the largest batch this chain may see (for exact grids)
+    int max_pblk;
+    int max_frames;
+};
+
+constexpr int N_STAGES = 9;  // bin, count, scan, tile, merge, flatten, scan roots, rank, final
+
+// Enqueues the chain; when stage_events is non-null (N_STAGES + 1 events) an
+// event is recorded before the first kernel and after each kernel.
+hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const LaunchCfg& cfg,
+                        hipStream_t stream, hipEvent_t* stage_events = nullptr);
+
+}  // namespace lidarseg

@@ -1,0 +1,251 @@
+"""Thin ctypes binding of liblidarseg (include/lidarseg.h).
+
+Argument marshalling only: every stage of the path runs in the HIP library.
+PyTorch supplies device memory (tensors) and streams.  The binding refuses to
+run without the built library; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblidarseg.so")
+
+LIDAR_OK = 0
+LIDAR_EINVAL = -1
+LIDAR_ENOMEM = -2
+LIDAR_EDEVICE = -3
+LIDAR_MAX_RINGS = 128
+
+LIDAR_LAUNCH_PLAIN = 0
+LIDAR_LAUNCH_BATCHED = 1
+LIDAR_LAUNCH_GRAPH = 2
+LAUNCH = {"plain": LIDAR_LAUNCH_PLAIN, "batched": LIDAR_LAUNCH_BATCHED, "graph": LIDAR_LAUNCH_GRAPH}
+
+# every symbol include/lidarseg.h declares
+EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lidar_last_error",
+           "lidar_query_sizes", "lidar_mesh_segment", "lidar_ctx_set_tuning", "lidar_ctx_set_profiling",
+           "lidar_ctx_stage_times")
+LIDAR_N_STAGES = 9
+STAGES = ("bin", "count", "scan", "tile", "merge", "flatten", "scan_roots", "rank", "final")
+
+
+class LidarError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblidarseg error {code}: {msg}")
+        self.code = code
+
+
+class lidar_sensor_t(ctypes.Structure):
+    _fields_ = [("n_rings", ctypes.c_int32), ("n_azimuth", ctypes.c_int32),
+                ("subsample", ctypes.c_int32), ("wrap", ctypes.c_int32),
+                ("elev_rad", ctypes.POINTER(ctypes.c_double)), ("az0_rad", ctypes.c_double)]
+
+
+class lidar_frame_t(ctypes.Structure):
+    _fields_ = [("sensor", ctypes.POINTER(lidar_sensor_t)), ("xyz", ctypes.c_void_p),
+                ("n_points", ctypes.c_int64), ("normals_in", ctypes.c_void_p)]
+
+
+class lidar_params_t(ctypes.Structure):
+    _fields_ = [("r_min", ctypes.c_double), ("r_max", ctypes.c_double), ("thr", ctypes.c_double * 3)]
+
+
+class lidar_result_t(ctypes.Structure):
+    _fields_ = [("vertices", ctypes.c_void_p), ("normals", ctypes.c_void_p),
+                ("labels", ctypes.c_void_p), ("triangles", ctypes.c_void_p),
+                ("vertex_point", ctypes.c_void_p), ("counts", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblidarseg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2005_02704_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    L.lidar_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    L.lidar_ctx_create.restype = ctypes.c_int
+    L.lidar_ctx_destroy.argtypes = [P]
+    L.lidar_ctx_destroy.restype = None
+    L.lidar_ctx_last_error.argtypes = [P]
+    L.lidar_ctx_last_error.restype = ctypes.c_char_p
+    L.lidar_last_error.argtypes = []
+    L.lidar_last_error.restype = ctypes.c_char_p
+    L.lidar_query_sizes.argtypes = [ctypes.POINTER(lidar_sensor_t), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    L.lidar_query_sizes.restype = ctypes.c_int
+    L.lidar_mesh_segment.argtypes = [P, ctypes.POINTER(lidar_frame_t), ctypes.c_int32,
+                                     ctypes.POINTER(lidar_params_t), ctypes.POINTER(lidar_result_t),
+                                     P, ctypes.c_int32]
+    L.lidar_mesh_segment.restype = ctypes.c_int
+    L.lidar_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    L.lidar_ctx_set_tuning.restype = ctypes.c_int
+    L.lidar_ctx_set_profiling.argtypes = [P, ctypes.c_int32]
+    L.lidar_ctx_set_profiling.restype = ctypes.c_int
+    L.lidar_ctx_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.lidar_ctx_stage_times.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+@dataclass
+class SensorGeometry:
+    """Host description of a sensor: ring elevations (radians, descending), firings, s."""
+    elev_rad: np.ndarray
+    n_azimuth: int
+    subsample: int = 1
+    wrap: int = 1
+    az0_rad: float = 0.0
+    _c: lidar_sensor_t = field(default=None, repr=False)
+    _elev: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def n_rings(self) -> int:
+        return int(len(self.elev_rad))
+
+    @property
+    def n_cols(self) -> int:
+        return self.n_azimuth // self.subsample
+
+    def c_struct(self) -> lidar_sensor_t:
+        if self._c is None:
+            self._elev = np.ascontiguousarray(self.elev_rad, dtype=np.float64)
+            self._c = lidar_sensor_t(self.n_rings, int(self.n_azimuth), int(self.subsample), int(self.wrap),
+                                     self._elev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     float(self.az0_rad))
+        return self._c
+
+
+def lidar_query_sizes(sensor: SensorGeometry):
+    L = load_library()
+    v = ctypes.c_int64()
+    t = ctypes.c_int64()
+    rc = L.lidar_query_sizes(ctypes.byref(sensor.c_struct()), ctypes.byref(v), ctypes.byref(t))
+    if rc != LIDAR_OK:
+        raise LidarError(rc, L.lidar_last_error().decode())
+    return int(v.value), int(t.value)
+
+
+class Outputs:
+    """Caller-owned device outputs of one frame (torch tensors at full capacity)."""
+
+    def __init__(self, sensor: SensorGeometry, device, with_vertex_point=True):
+        import torch
+        V, T = lidar_query_sizes(sensor)
+        self.vertices = torch.empty((max(V, 1), 3), dtype=torch.float32, device=device)
+        self.normals = torch.empty((max(V, 1), 3), dtype=torch.float32, device=device)
+        self.labels = torch.empty(max(V, 1), dtype=torch.int32, device=device)
+        self.triangles = torch.empty((max(T, 1), 3), dtype=torch.int32, device=device)
+        self.vertex_point = torch.empty(max(V, 1), dtype=torch.int32, device=device) if with_vertex_point else None
+        self.counts = torch.zeros(3, dtype=torch.int64, device=device)
+
+    def c_struct(self) -> lidar_result_t:
+        return lidar_result_t(self.vertices.data_ptr(), self.normals.data_ptr(), self.labels.data_ptr(),
+                              self.triangles.data_ptr(),
+                              self.vertex_point.data_ptr() if self.vertex_point is not None else None,
+                              self.counts.data_ptr())
+
+    def trimmed(self):
+        """Views cut to the counts (synchronises with the device to read them)."""
+        V, T, K = (int(x) for x in self.counts.cpu())
+        return dict(vertices=self.vertices[:V], normals=self.normals[:V], labels=self.labels[:V],
+                    triangles=self.triangles[:T],
+                    vertex_point=self.vertex_point[:V] if self.vertex_point is not None else None,
+                    counts=(V, T, K))
+
+
+class LidarContext:
+    """A lidar_ctx: device workspace and captured graph, used by one thread at a time."""
+
+    def __init__(self, device: int = 0):
+        self._L = load_library()
+        self._h = ctypes.c_void_p()
+        rc = self._L.lidar_ctx_create(int(device), ctypes.byref(self._h))
+        if rc != LIDAR_OK:
+            raise LidarError(rc, self._L.lidar_last_error().decode())
+        self.device = device
+
+    def close(self):
+        if self._h:
+            self._L.lidar_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, grid_workgroups: int = 0, tile_cells: int = 0):
+        rc = self._L.lidar_ctx_set_tuning(self._h, int(grid_workgroups), int(tile_cells))
+        self._check(rc)
+
+    def set_profiling(self, enable: bool):
+        self._check(self._L.lidar_ctx_set_profiling(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} since the last call; waits for the timed work."""
+        ms = (ctypes.c_double * LIDAR_N_STAGES)()
+        n = (ctypes.c_int64 * LIDAR_N_STAGES)()
+        self._check(self._L.lidar_ctx_stage_times(self._h, ms, n))
+        return {name: (float(ms[k]), int(n[k])) for k, name in enumerate(STAGES)}
+
+    def _check(self, rc):
+        if rc != LIDAR_OK:
+            raise LidarError(rc, self._L.lidar_ctx_last_error(self._h).decode())
+
+    def prepare(self, inputs, params: lidar_params_t, outputs):
+        """Build the C argument arrays once (for repeated launches on the same buffers)."""
+        n = len(inputs)
+        frames = (lidar_frame_t * n)()
+        results = (lidar_result_t * n)()
+        keep = []
+        for f, (xyz, sensor, normals_in) in enumerate(inputs):
+            sc = sensor.c_struct()
+            keep.append(sc)
+            frames[f] = lidar_frame_t(ctypes.pointer(sc), xyz.data_ptr() if xyz.numel() else None,
+                                      int(xyz.shape[0]),
+                                      normals_in.data_ptr() if normals_in is not None else None)
+            results[f] = outputs[f].c_struct()
+        return (frames, n, params, results, keep)
+
+    def lidar_mesh_segment(self, prepared, stream=None, launch: str | int = "batched"):
+        """Enqueue lidar_mesh_segment on `stream` (torch stream; default: current)."""
+        import torch
+        frames, n, params, results, _keep = prepared
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        mode = LAUNCH[launch] if isinstance(launch, str) else int(launch)
+        rc = self._L.lidar_mesh_segment(self._h, frames, n, ctypes.byref(params), results,
+                                        ctypes.c_void_p(stream.cuda_stream), mode)
+        self._check(rc)
+
+
+def make_params(r_min=1.0, r_max=60.0, thr=(0.2, 0.2, 0.2)) -> lidar_params_t:
+    return lidar_params_t(float(r_min), float(r_max), (ctypes.c_double * 3)(*[float(t) for t in thr]))
+
+
+def lidar_mesh_segment(ctx: LidarContext, inputs, params: lidar_params_t | None = None,
+                       launch: str = "batched", stream=None, with_vertex_point=True):
+    """Convenience: inputs = [(xyz cuda float32 [N,3], SensorGeometry, normals_in or None)].
+
+    Allocates outputs, enqueues the call and returns the Outputs objects (call
+    .trimmed() to synchronise and cut them to their counts)."""
+    import torch
+    params = params or make_params()
+    dev = torch.device("cuda", ctx.device)
+    outs = [Outputs(s, dev, with_vertex_point) for (_x, s, _n) in inputs]
+    prep = ctx.prepare(inputs, params, outs)
+    ctx.lidar_mesh_segment(prep, stream=stream, launch=launch)
+    return outs

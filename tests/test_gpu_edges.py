@@ -1,0 +1,114 @@
+"""GPU edge cases against the oracle: empty and degenerate sweeps, seams, ragged tiles."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import check_geometry, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_02704_amd as lp
+    c = lp.LidarContext(0)
+    yield c
+    c.close()
+
+
+def _both(ctx, xyz, sen, s=1, wrap=1, **kw):
+    g = run_gpu(ctx, [(xyz, sen, s, wrap, None)], **kw)[0]
+    r = run_oracle(xyz, sen, s, wrap, **kw)
+    check_geometry(g, r)
+    assert g["counts"][2] == r.counts[2]
+    assert np.array_equal(g["labels"], r.labels)
+    return g, r
+
+
+def test_empty_sweep(ctx):
+    sen = synth.Sensor.standard(16, 1024)
+    g, r = _both(ctx, np.zeros((0, 3), np.float32), sen)
+    assert g["counts"] == (0, 0, 0)
+
+
+def test_all_points_out_of_range(ctx):
+    f = synth.workload_frames("c1_16x1800")[0]
+    g, _ = _both(ctx, f.xyz, f.sensor, r_min=500.0, r_max=600.0)
+    assert g["counts"] == (0, 0, 0)
+
+
+def test_single_point(ctx):
+    sen = synth.Sensor.standard(16, 1024)
+    g, _ = _both(ctx, np.array([[10.0, 0.0, -0.5]], np.float32), sen)
+    assert g["counts"] == (1, 0, 1)
+
+
+def test_single_ring(ctx):
+    sen = synth.Sensor(1, 720, 0.0, 0.0)
+    ang = np.arange(720) * 2 * math.pi / 720
+    xyz = np.stack([10 * np.cos(ang), 10 * np.sin(ang), np.zeros(720)], 1).astype(np.float32)
+    g, _ = _both(ctx, xyz, sen)
+    assert g["counts"] == (720, 0, 720)
+    assert not np.any(g["normals"])
+
+
+@pytest.mark.parametrize("W,s,wrap", [(3, 1, 1), (4, 1, 1), (6, 2, 1), (5, 1, 0), (1, 1, 0), (2, 1, 0)])
+def test_tiny_lattices(ctx, W, s, wrap):
+    sen = synth.Sensor(5, W, 10.0, -10.0)
+    rng = np.random.Generator(np.random.PCG64(W * 10 + s))
+    U = sen.rays().transpose(1, 0, 2).reshape(-1, 3)
+    r = rng.uniform(5, 6, size=U.shape[0])
+    keep = rng.random(U.shape[0]) < 0.85
+    xyz = (U * r[:, None])[keep].astype(np.float32)
+    _both(ctx, xyz, sen, s, wrap)
+
+
+@pytest.mark.parametrize("H,W", [(7, 1000), (128, 1800), (100, 333), (33, 4097), (16, 1800)])
+def test_ragged_tiles_and_odd_ring_counts(ctx, H, W):
+    sen = synth.Sensor(H, W, 12.0, -24.0)
+    f = synth.make_frame(sen, "street", H * 7 + W, sigma=0.01, dropout=0.2)
+    g = run_gpu(ctx, [(f.xyz, sen, 1, 1, None)])[0]
+    r = run_oracle(f.xyz, sen, 1, 1)
+    check_geometry(g, r)
+    nin_g = run_gpu(ctx, [(f.xyz, sen, 1, 1, r.normals)])[0]
+    assert np.array_equal(nin_g["labels"], r.labels)
+
+
+def test_open_sweep_without_seam(ctx):
+    f = synth.workload_frames("c2_64x2048")[0]
+    r = run_oracle(f.xyz, f.sensor, 2, 0)
+    g = run_gpu(ctx, [(f.xyz, f.sensor, 2, 0, r.normals)])[0]
+    check_geometry(g, r)
+    assert np.array_equal(g["labels"], r.labels)
+
+
+def test_non_finite_and_duplicate_points(ctx):
+    f = synth.workload_frames("c1_16x1800")[0]
+    xyz = f.xyz.copy()
+    xyz[3, 0] = np.nan
+    xyz[50, 2] = np.inf
+    dup = np.concatenate([xyz, xyz[::7], xyz[::5] * np.float32(1.0001)])
+    _both(ctx, dup, f.sensor)
+
+
+def test_noise_free_ground_normals_bitwise(ctx):
+    sen = synth.Sensor.standard(32, 1024)
+    f = synth.make_frame(sen, "ground", 2, sigma=0.0, dropout=0.0)
+    g, r = _both(ctx, f.xyz, sen)
+    has = np.any(g["normals"] != 0, axis=1)
+    assert np.all(g["normals"][has] == np.float32([0, 0, -1]))
+    assert np.array_equal(g["normals"], r.normals)
+
+
+def test_repeat_runs_bitwise(ctx):
+    f = synth.workload_frames("c4_128x4096")[0]
+    a = run_gpu(ctx, [(f.xyz, f.sensor, 2, 1, None)], launch="batched")[0]
+    for _ in range(3):
+        b = run_gpu(ctx, [(f.xyz, f.sensor, 2, 1, None)], launch="batched")[0]
+        for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
+            assert np.array_equal(a[k], b[k])
