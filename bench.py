@@ -61,6 +61,11 @@ def main():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-cells", type=int, default=0, help="0 = library default")
+    ap.add_argument("--grid", type=int, default=0, help="workgroups per batched stage, 0 = library default")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (3 times), as the yardstick "
+                         "for HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -75,6 +80,16 @@ def main():
     import paper_2005_02704_amd as lp
     import synth
 
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB device copy done")
+        del src, dst
+
     log(f"generating {args.frames} sweeps (seed {args.seed})")
     t0 = time.time()
     frames = synth.batch_frames(args.frames, args.seed)
@@ -83,12 +98,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = lp.LidarContext(0)
+    ctx.set_tuning(args.grid, args.tile_cells)
     params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2))
     geos = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, 1, 1, f.sensor.az0) for f in frames]
     inputs = [(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)]
     outs = [lp.Outputs(g, dev) for g in geos]
     prep = ctx.prepare(inputs, params, outs)
     stream = torch.cuda.current_stream(dev)
+
+    host_ms = {}
 
     def run(launch, steps, warmup):
         for _ in range(warmup):
@@ -97,6 +115,7 @@ def main():
         t = time.perf_counter()
         for _ in range(steps):
             ctx.lidar_mesh_segment(prep, stream, launch)
+        host_ms[launch] = (time.perf_counter() - t) * 1000.0 / steps
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1000.0 / steps
 
@@ -104,13 +123,13 @@ def main():
     ms_graph = run("graph", args.steps, args.warmup)
     counts = np.array([[int(x) for x in o.counts.cpu()] for o in outs])
     V, T = int(counts[:, 0].sum()), int(counts[:, 1].sum())
-    log(f"  graph: {ms_graph:.3f} ms/step  V={V} T={T}")
+    log(f"  graph: {ms_graph:.3f} ms/step (host enqueue {host_ms['graph']:.3f} ms/step)  V={V} T={T}")
     log("timing batched launches")
     ms_batched = run("batched", args.steps, args.warmup)
-    log(f"  batched: {ms_batched:.3f} ms/step")
+    log(f"  batched: {ms_batched:.3f} ms/step (host enqueue {host_ms['batched']:.3f} ms/step)")
     log("timing plain per-frame chains")
     ms_plain = run("plain", args.steps, args.warmup)
-    log(f"  plain: {ms_plain:.3f} ms/step")
+    log(f"  plain: {ms_plain:.3f} ms/step (host enqueue {host_ms['plain']:.3f} ms/step)")
 
     # dominant kernel: per-stage HIP events on the launch stream over K batched steps
     log("timing stages with HIP events")

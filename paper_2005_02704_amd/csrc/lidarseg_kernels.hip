@@ -116,6 +116,7 @@ __device__ __forceinline__ int nearest_ring(const double* e, int H, double el) {
 // then the lower index: independent of thread order.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int PPT = POINT_BLOCK / NT;  // points per thread per item
     __shared__ double s_elev[MAX_RINGS];
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
@@ -135,12 +136,25 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
         const double az0 = fd->az0, dphi = fd->dphi, rmin2 = fd->rmin2, rmax2 = fd->rmax2;
         const float* __restrict__ xyz = fd->xyz;
         unsigned long long* keys = reinterpret_cast<unsigned long long*>(ws.keys + fd->cell_off);
-        const int64_t p0 = (int64_t)(b - fd->pblk_off) * POINT_BLOCK;
-        const int64_t p1 = min(p0 + POINT_BLOCK, fd->n_points);
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += NT) {
-            const float xf = xyz[3 * p], yf = xyz[3 * p + 1], zf = xyz[3 * p + 2];
-            if (!(isfinite(xf) && isfinite(yf) && isfinite(zf))) continue;
-            const double x = xf, y = yf, z = zf;
+        const int64_t p0 = (int64_t)(b - fd->pblk_off) * POINT_BLOCK + threadIdx.x;
+        const int64_t np = fd->n_points;
+        // all loads of the item first, so their latencies overlap
+        float px[PPT], py[PPT], pz[PPT];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+            const int64_t p = p0 + r * NT;
+            px[r] = py[r] = pz[r] = __builtin_nanf("");
+            if (p < np) {
+                px[r] = xyz[3 * p];
+                py[r] = xyz[3 * p + 1];
+                pz[r] = xyz[3 * p + 2];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+            const int64_t p = p0 + r * NT;
+            if (!(isfinite(px[r]) && isfinite(py[r]) && isfinite(pz[r]))) continue;
+            const double x = px[r], y = py[r], z = pz[r];
             const double rho2 = x * x + y * y;   // products of floats are exact in FP64
             const double r2 = rho2 + z * z;
             if (r2 < rmin2 || r2 > rmax2) continue;
@@ -273,54 +287,90 @@ __device__ __forceinline__ bool similar(float ax, float ay, float az, float bx, 
            fabs((double)az - (double)bz) < tz;
 }
 
+// FP64 reciprocal and reciprocal square root: hardware estimate plus two Newton
+// steps (relative error far below 1e-15; the weights and the final scaling need
+// no correctly rounded division).
+__device__ __forceinline__ double rcp_dp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ double rsq_dp(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double r = fma(-h * y, y, 0.5);
+    y = fma(y, r, y);
+    r = fma(-h * y, y, 0.5);
+    return fma(y, r, y);
+}
+
+// x / H for the small non-negative LDS indices used here (x < 2^13, H <= 128).
+__device__ __forceinline__ int div_small(int x, float inv_h) {
+    return (int)(((float)x + 0.5f) * inv_h);
+}
+
 // Weighted normal of LDS cell lx (ring i): sum over cycle-adjacent present pairs
 // (A,B),(B,C),(C,D),(D,E),(E,F),(F,A) of (V_t x V_u) / (|V_t| + |V_u|), scaled to
-// unit length (Section 2, Normal Estimation).  Edge vectors are exact in FP64.
+// unit length (Section 2, Normal Estimation).  Edge vectors are exact in FP64;
+// empty cells hold NaN coordinates.
 __device__ __forceinline__ void vertex_normal(const float* sx, const float* sy, const float* sz,
-                                              const uint8_t* sflag, int lx, int i, int H,
-                                              float& onx, float& ony, float& onz) {
+                                              int lx, int i, int H, float& onx, float& ony, float& onz) {
     const bool up = i >= 1, dn = i + 1 < H;
-    const int off[6] = {1, H + 1, H, -1, -H - 1, -H};
-    bool pres[6];
-    pres[0] = dn && sflag[lx + 1];
-    pres[1] = dn && sflag[lx + H + 1];
-    pres[2] = sflag[lx + H] != 0;
-    pres[3] = up && sflag[lx - 1];
-    pres[4] = up && sflag[lx - H - 1];
-    pres[5] = sflag[lx - H] != 0;
+    const int q[6] = {lx + 1, lx + H + 1, lx + H, lx - 1, lx - H - 1, lx - H};
+    const bool ok[6] = {dn, dn, true, up, up, true};
     const double px = sx[lx], py = sy[lx], pz = sz[lx];
-    double vx[6], vy[6], vz[6], len[6];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        if (pres[t]) {
-            const int q = lx + off[t];
-            vx[t] = (double)sx[q] - px;
-            vy[t] = (double)sy[q] - py;
-            vz[t] = (double)sz[q] - pz;
-            len[t] = sqrt(vx[t] * vx[t] + vy[t] * vy[t] + vz[t] * vz[t]);
-        } else {
-            vx[t] = vy[t] = vz[t] = len[t] = 0.0;
+    double v0x = 0.0, v0y = 0.0, v0z = 0.0, l0 = 0.0;
+    bool p0 = false;
+    if (ok[0]) {
+        const float qx = sx[q[0]];
+        if (qx == qx) {
+            p0 = true;
+            v0x = (double)qx - px;
+            v0y = (double)sy[q[0]] - py;
+            v0z = (double)sz[q[0]] - pz;
+            const double l2 = v0x * v0x + v0y * v0y + v0z * v0z;
+            l0 = l2 * rsq_dp(l2);
         }
     }
+    double vpx = v0x, vpy = v0y, vpz = v0z, lp = l0;
+    bool pp = p0;
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool any = false;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const int u = (t + 1) % 6;
-        if (pres[t] && pres[u]) {
-            const double w = 1.0 / (len[t] + len[u]);
-            ax += w * (vy[t] * vz[u] - vz[t] * vy[u]);
-            ay += w * (vz[t] * vx[u] - vx[t] * vz[u]);
-            az += w * (vx[t] * vy[u] - vy[t] * vx[u]);
+    for (int t = 1; t <= 6; ++t) {
+        double vx = 0.0, vy = 0.0, vz = 0.0, lc = 0.0;
+        bool pc = false;
+        if (t == 6) {
+            vx = v0x; vy = v0y; vz = v0z; lc = l0; pc = p0;
+        } else if (ok[t]) {
+            const float qx = sx[q[t]];
+            if (qx == qx) {
+                pc = true;
+                vx = (double)qx - px;
+                vy = (double)sy[q[t]] - py;
+                vz = (double)sz[q[t]] - pz;
+                const double l2 = vx * vx + vy * vy + vz * vz;
+                lc = l2 * rsq_dp(l2);
+            }
+        }
+        if (pp && pc) {
+            const double w = rcp_dp(lp + lc);
+            ax = fma(w, vpy * vz - vpz * vy, ax);
+            ay = fma(w, vpz * vx - vpx * vz, ay);
+            az = fma(w, vpx * vy - vpy * vx, az);
             any = true;
         }
+        vpx = vx; vpy = vy; vpz = vz; lp = lc; pp = pc;
     }
     const double n2 = ax * ax + ay * ay + az * az;
     if (any && n2 > 0.0) {
-        const double nrm = sqrt(n2);
-        onx = (float)(ax / nrm);
-        ony = (float)(ay / nrm);
-        onz = (float)(az / nrm);
+        const double inv = rsq_dp(n2);
+        onx = (float)(ax * inv);
+        ony = (float)(ay * inv);
+        onz = (float)(az * inv);
     } else {
         onx = ony = onz = 0.0f;
     }
@@ -328,28 +378,29 @@ __device__ __forceinline__ void vertex_normal(const float* sx, const float* sy, 
 
 // ---------------------------------------------------------------------------
 // The per-tile fused stage.  LDS columns lc = -1 .. TWe+1 of the tile (global
-// column k0 + lc, wrapped on a closed cylinder) hold validity and coordinates;
-// LDS cell lx = (lc + 1) * H + i.  Own cells are lc in [0, TWe); the right
-// column lc = TWe belongs to the next tile but its normals are needed for the
-// joins that leave the tile.
+// column k0 + lc, wrapped on a closed cylinder) hold the kept points'
+// coordinates (NaN = empty cell); LDS cell lx = (lc + 1) * H + i.  Own cells are
+// lc in [0, TWe); the right column lc = TWe belongs to the next tile but its
+// normals are needed for the joins that leave the tile.  Index l = lx - H runs
+// over own cells and then the right column.
 template <int NT, int MAXC>
 __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int XC = MAXC + 3 * MAX_RINGS;  // coordinate cells incl. halo
     constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
+    constexpr int RX = (XC + NT - 1) / NT;
+    constexpr int RN = (NC + NT - 1) / NT;
+    // sx/sy/sz: coordinates, then (after the normal stage) normals indexed by l
     __shared__ float sx[XC], sy[XC], sz[XC];
-    __shared__ float snx[NC], sny[NC], snz[NC];
-    __shared__ int svid[NC];
-    __shared__ uint8_t sflag[XC];
+    __shared__ int svid[NC];     // vertex index of l (frame-local), -1 = empty
+    __shared__ int saux[MAXC];   // kept point index, then triangle start, then union-find parent
     __shared__ int s_tmp[NT / 64];
-    int* const sparent = reinterpret_cast<int*>(sx);   // after the normal stage
-    int* const ssrc = reinterpret_cast<int*>(snx);     // before the normal stage
-    int* const stri = reinterpret_cast<int*>(snx);     // same slots, after ssrc is read
 
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
     for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
         const FrameDesc* fd = F + frame_of_tile(F, nf, t);
         const int H = fd->H, Wp = fd->Wp, wrap = fd->wrap;
+        const float inv_h = 1.0f / (float)H;
         const int lt = t - fd->tile_off;
         const int k0 = lt * fd->TW;
         const int TWe = min(fd->TW, Wp - k0);
@@ -359,28 +410,48 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
         const uint64_t* keys = ws.keys + fd->cell_off;
         const float* __restrict__ xyz = fd->xyz;
         const float* __restrict__ nin = fd->normals_in;
+        const int64_t np = fd->n_points;
         const double tx = fd->thr[0], ty = fd->thr[1], tz = fd->thr[2];
 
         __syncthreads();  // LDS of the previous tile is free
-        // 1. validity and coordinates of the tile and its halo columns
-        for (int lx = threadIdx.x; lx < nx; lx += NT) {
-            const int col = lx / H;
-            const int i = lx - col * H;
-            int k = k0 + col - 1;
-            bool in = true;
-            if (k < 0 || k >= Wp) {
-                if (wrap) k = (k < 0) ? k + Wp : k - Wp;
-                else in = false;
+        // 1. keys of the tile and its halo columns, then the kept points (loads
+        //    issued back to back so their latencies overlap)
+        uint64_t key[RX];
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            const int lx = threadIdx.x + r * NT;
+            key[r] = KEY_EMPTY;
+            if (lx < nx) {
+                const int col = div_small(lx, inv_h);
+                const int i = lx - col * H;
+                int k = k0 + col - 1;
+                bool in = true;
+                if (k < 0 || k >= Wp) {
+                    if (wrap) k = (k < 0) ? k + Wp : k - Wp;
+                    else in = false;
+                }
+                if (in) key[r] = keys[(int64_t)k * H + i];
             }
-            const uint64_t key = in ? keys[(int64_t)k * H + i] : KEY_EMPTY;
-            const bool v = occupied(key, fd->n_points);
-            sflag[lx] = v;
-            if (v) {
-                const uint32_t src = (uint32_t)key;
-                sx[lx] = xyz[3 * (int64_t)src];
-                sy[lx] = xyz[3 * (int64_t)src + 1];
-                sz[lx] = xyz[3 * (int64_t)src + 2];
-                if (lx >= H && lx < H + nown) ssrc[lx - H] = (int)src;
+        }
+        float cx[RX], cy[RX], cz[RX];
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            cx[r] = cy[r] = cz[r] = __builtin_nanf("");
+            if (occupied(key[r], np)) {
+                const float* q = xyz + 3 * (int64_t)(uint32_t)key[r];
+                cx[r] = q[0];
+                cy[r] = q[1];
+                cz[r] = q[2];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            const int lx = threadIdx.x + r * NT;
+            if (lx < nx) {
+                sx[lx] = cx[r];
+                sy[lx] = cy[r];
+                sz[lx] = cz[r];
+                if (lx >= H && lx < H + nown) saux[lx - H] = (int)(uint32_t)key[r];
             }
         }
         __syncthreads();
@@ -397,15 +468,19 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
         for (int base = 0; base < nscan; base += NT) {
             const int l = base + threadIdx.x;
             int val = 0;
-            if (l < nscan && sflag[l + H]) {
-                int ntri = 0;
-                const int i = l - (l / H) * H;
-                if (l < nown && i + 1 < H) {
-                    const int lx = l + H;
-                    const bool a = sflag[lx + 1], b = sflag[lx + H + 1], c = sflag[lx + H];
-                    ntri = (int)(a && b) + (int)(b && c);
+            if (l < nscan) {
+                const int lx = l + H;
+                if (sx[lx] == sx[lx]) {
+                    int ntri = 0;
+                    const int i = l - div_small(l, inv_h) * H;
+                    if (l < nown && i + 1 < H) {
+                        const bool a = sx[lx + 1] == sx[lx + 1];
+                        const bool b = sx[lx + H + 1] == sx[lx + H + 1];
+                        const bool c = sx[lx + H] == sx[lx + H];
+                        ntri = (int)(a && b) + (int)(b && c);
+                    }
+                    val = 1 | (ntri << 16);
                 }
-                val = 1 | (ntri << 16);
             }
             int tot;
             const int ex = block_excl_scan<NT>(val, tot, s_tmp);
@@ -421,8 +496,8 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
                     vo[0] = sx[lx];
                     vo[1] = sy[lx];
                     vo[2] = sz[lx];
-                    if (fd->vpoint) fd->vpoint[vid] = ssrc[l];
-                    stri[l] = tbase + ext;
+                    if (fd->vpoint) fd->vpoint[vid] = saux[l];
+                    saux[l] = tbase + ext;
                 }
             }
             carry_v += tot & 0xFFFF;
@@ -433,10 +508,10 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
         // 3. triangles T_a = (p, A, B), T_b = (p, B, C) of each own anchor
         for (int l = threadIdx.x; l < nown; l += NT) {
             const int p = svid[l];
-            const int i = l - (l / H) * H;
+            const int i = l - div_small(l, inv_h) * H;
             if (p < 0 || i + 1 >= H) continue;
             const int a = svid[l + 1], b = svid[l + H + 1], c = svid[l + H];
-            int ti = stri[l];
+            int ti = saux[l];
             if (a >= 0 && b >= 0) {
                 int32_t* to = fd->tris + 3 * (int64_t)ti;
                 to[0] = p; to[1] = a; to[2] = b;
@@ -447,46 +522,60 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
                 to[0] = p; to[1] = b; to[2] = c;
             }
         }
-        __syncthreads();
 
-        // 4. normals of own cells and the right column (or the given ones)
-        for (int l = threadIdx.x; l < nscan; l += NT) {
-            const int lx = l + H;
-            const int i = l - (l / H) * H;
-            float nx_ = 0.0f, ny_ = 0.0f, nz_ = 0.0f;
-            const int vid = svid[l];
-            if (vid >= 0) {
-                if (nin) {
-                    nx_ = nin[3 * (int64_t)vid];
-                    ny_ = nin[3 * (int64_t)vid + 1];
-                    nz_ = nin[3 * (int64_t)vid + 2];
-                } else {
-                    vertex_normal(sx, sy, sz, sflag, lx, i, H, nx_, ny_, nz_);
-                }
-                if (l < nown) {
-                    float* no = fd->normals + 3 * (int64_t)vid;
-                    no[0] = nx_; no[1] = ny_; no[2] = nz_;
+        // 4. normals of own cells and the right column (or the given ones), kept
+        //    in registers until every thread is done reading coordinates
+        float nrm[RN][3];
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int l = threadIdx.x + r * NT;
+            nrm[r][0] = nrm[r][1] = nrm[r][2] = 0.0f;
+            if (l < nscan) {
+                const int vid = svid[l];
+                if (vid >= 0) {
+                    if (nin) {
+                        nrm[r][0] = nin[3 * (int64_t)vid];
+                        nrm[r][1] = nin[3 * (int64_t)vid + 1];
+                        nrm[r][2] = nin[3 * (int64_t)vid + 2];
+                    } else {
+                        const int i = l - div_small(l, inv_h) * H;
+                        vertex_normal(sx, sy, sz, l + H, i, H, nrm[r][0], nrm[r][1], nrm[r][2]);
+                    }
+                    if (l < nown) {
+                        float* no = fd->normals + 3 * (int64_t)vid;
+                        no[0] = nrm[r][0];
+                        no[1] = nrm[r][1];
+                        no[2] = nrm[r][2];
+                    }
                 }
             }
-            snx[l] = nx_; sny[l] = ny_; snz[l] = nz_;
         }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l < nscan) {
+                sx[l] = nrm[r][0];
+                sy[l] = nrm[r][1];
+                sz[l] = nrm[r][2];
+            }
+        }
+        for (int l = threadIdx.x; l < nown; l += NT) saux[l] = l;
         __syncthreads();
 
         // 5. segments inside the tile: union over similar joins C, A, B
-        for (int l = threadIdx.x; l < nown; l += NT) sparent[l] = l;
-        __syncthreads();
+        int* const sparent = saux;
         for (int l = threadIdx.x; l < nown; l += NT) {
-            const int i = l - (l / H) * H;
-            const int lc = l / H;
-            const float ax = snx[l], ay = sny[l], az = snz[l];
+            const int lc = div_small(l, inv_h);
+            const int i = l - lc * H;
+            const float ax = sx[l], ay = sy[l], az = sz[l];
             if (ax == 0.0f && ay == 0.0f && az == 0.0f) continue;
-            if (i + 1 < H && similar(ax, ay, az, snx[l + 1], sny[l + 1], snz[l + 1], tx, ty, tz))
+            if (i + 1 < H && similar(ax, ay, az, sx[l + 1], sy[l + 1], sz[l + 1], tx, ty, tz))
                 lds_union(sparent, l, l + 1);
             if (lc + 1 < TWe) {
-                if (similar(ax, ay, az, snx[l + H], sny[l + H], snz[l + H], tx, ty, tz))
+                if (similar(ax, ay, az, sx[l + H], sy[l + H], sz[l + H], tx, ty, tz))
                     lds_union(sparent, l, l + H);
-                if (i + 1 < H &&
-                    similar(ax, ay, az, snx[l + H + 1], sny[l + H + 1], snz[l + H + 1], tx, ty, tz))
+                if (i + 1 < H && similar(ax, ay, az, sx[l + H + 1], sy[l + H + 1], sz[l + H + 1], tx, ty, tz))
                     lds_union(sparent, l, l + H + 1);
             }
         }
@@ -495,10 +584,9 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
         for (int i = threadIdx.x; i < H; i += NT) {
             const int l = (TWe - 1) * H + i;
             int2 ec = make_int2(-1, -1), eb = make_int2(-1, -1);
-            if (similar(snx[l], sny[l], snz[l], snx[l + H], sny[l + H], snz[l + H], tx, ty, tz))
+            if (similar(sx[l], sy[l], sz[l], sx[l + H], sy[l + H], sz[l + H], tx, ty, tz))
                 ec = make_int2(svid[l], svid[l + H]);
-            if (i + 1 < H &&
-                similar(snx[l], sny[l], snz[l], snx[l + H + 1], sny[l + H + 1], snz[l + H + 1], tx, ty, tz))
+            if (i + 1 < H && similar(sx[l], sy[l], sz[l], sx[l + H + 1], sy[l + H + 1], sz[l + H + 1], tx, ty, tz))
                 eb = make_int2(svid[l], svid[l + H + 1]);
             border[2 * i] = ec;
             border[2 * i + 1] = eb;
@@ -543,17 +631,41 @@ __device__ __forceinline__ void g_union(int* P, int a, int b) {
     }
 }
 
+// Per tile: the similar joins leaving through its right edge.  Both ends are
+// replaced by their current parents (any ancestor works for a union), and a
+// join whose parent pair repeats one of the previous slots (the rows above,
+// usually the same two segments) is skipped, which keeps most threads of a
+// border off the same two roots.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_merge(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    static_assert(NT >= 2 * MAX_RINGS, "one border slot per thread");
+    __shared__ int2 s_pair[2 * MAX_RINGS];
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
     for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
         const FrameDesc* fd = F + frame_of_tile(F, nf, t);
         const int H = fd->H;
+        int* L = fd->labels;
         const int2* border = ws.border + fd->border_off + (int64_t)(t - fd->tile_off) * 2 * H;
-        for (int e = threadIdx.x; e < 2 * H; e += NT) {
+        const int e = threadIdx.x;
+        int2 rr = make_int2(-1, -1);
+        if (e < 2 * H) {
             const int2 ab = border[e];
-            if (ab.x >= 0) g_union(fd->labels, ab.x, ab.y);
+            if (ab.x >= 0) rr = make_int2(g_load(L + ab.x), g_load(L + ab.y));
+        }
+        __syncthreads();
+        if (e < 2 * H) s_pair[e] = rr;
+        __syncthreads();
+        if (rr.x >= 0) {
+            bool dup = false;
+#pragma unroll
+            for (int d = 1; d <= 4; ++d) {
+                if (e - d >= 0) {
+                    const int2 q = s_pair[e - d];
+                    dup |= (q.x == rr.x && q.y == rr.y);
+                }
+            }
+            if (!dup) g_union(L, rr.x, rr.y);
         }
     }
 }
