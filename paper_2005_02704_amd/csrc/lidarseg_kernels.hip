@@ -287,24 +287,17 @@ __device__ __forceinline__ bool similar(float ax, float ay, float az, float bx, 
            fabs((double)az - (double)bz) < tz;
 }
 
-// FP64 reciprocal and reciprocal square root: hardware estimate plus two Newton
-// steps (relative error far below 1e-15; the weights and the final scaling need
-// no correctly rounded division).
+// FP64 reciprocal and reciprocal square root: the hardware estimate (about 2^-26
+// relative error) plus one Newton step (about 2^-50).  Weights and the final
+// scaling need no correctly rounded division: the normal is rounded to FP32.
 __device__ __forceinline__ double rcp_dp(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
 }
 
 __device__ __forceinline__ double rsq_dp(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    double r = fma(-h * y, y, 0.5);
-    y = fma(y, r, y);
-    r = fma(-h * y, y, 0.5);
-    return fma(y, r, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    return fma(y, fma(-0.5 * x * y, y, 0.5), y);
 }
 
 // x / H for the small non-negative LDS indices used here (x < 2^13, H <= 128).
