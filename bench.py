@@ -47,8 +47,8 @@ def stage_bytes(stage, N, V, T):
     if stage == "tile":
         return 12 * V + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T  # kept xyz in; vertices,
         # normals, vertex_point, local labels, triangles out
-    if stage in ("flatten", "rank", "final"):
-        return 8 * V                          # label read + write
+    if stage == "label":
+        return 8 * V                          # forest entry read + label written
     return 0
 
 
@@ -98,7 +98,7 @@ def served_run(args, lp, synth, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--seed", type=int, default=2024)
@@ -154,8 +154,14 @@ def main():
     host_ms = {}
 
     def run(launch, steps, warmup):
-        for _ in range(warmup):
+        # W warmup steps, and at least half a second of this form, so clocks settle
+        t_w = time.perf_counter()
+        n_w = 0
+        while n_w < warmup or time.perf_counter() - t_w < 0.5:
             ctx.lidar_mesh_segment(prep, stream, launch)
+            n_w += 1
+            if n_w % 8 == 0:
+                torch.cuda.synchronize()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):

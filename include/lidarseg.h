@@ -65,7 +65,7 @@ typedef struct {
     int32_t subsample;       /* s >= 1, W % s == 0 (the paper's sampling interval) */
     int32_t wrap;            /* 1: join column W'-1 to column 0 (closed cylinder); 0: open */
     const double* elev_rad;  /* host, H ring elevations in radians, strictly descending */
-    double az0_rad;          /* azimuth of firing 0 */
+    double az0_rad;          /* azimuth of firing 0, in [-2 pi, 2 pi] */
 } lidar_sensor_t;
 
 /* One sweep. */
@@ -93,11 +93,12 @@ typedef struct {
 typedef struct {
     float* vertices;        /* device [V][3]: the kept input points, bit-exact */
     float* normals;         /* device [V][3]: unit normals, zero vector = no normal */
-    int32_t* labels;        /* device [V]: 1..K.  Also used as scratch while labelling */
+    int32_t* labels;        /* device [V]: 1..K */
     int32_t* triangles;     /* device [T][3]: vertex indices, each oriented so that
                                (v1-v0) x (v2-v0) points away from the sensor */
     int32_t* vertex_point;  /* device [V] or NULL: input index of each vertex */
-    int64_t* counts;        /* device [3]: V, T, K */
+    int64_t* counts;        /* device [3]: V, T, K; -1 if the frame's work failed on the
+                               device (a bounded wait expired; outputs are then invalid) */
 } lidar_result_t;
 
 /* Create a context on HIP device `device`.  The context owns its device
@@ -109,7 +110,8 @@ const char* lidar_ctx_last_error(const lidar_ctx* ctx);
 /* Message of the last failure outside any context (creation, size queries). */
 const char* lidar_last_error(void);
 
-/* Output capacities for one frame of this sensor: V <= H*W', T <= 2*(H-1)*W'. */
+/* Output capacities for one frame of this sensor: V <= H*W', T <= 2*(H-1)*W'.
+ * A lattice may hold at most 2^29 cells. */
 int lidar_query_sizes(const lidar_sensor_t* sensor, int64_t* max_vertices,
                       int64_t* max_triangles);
 
@@ -127,9 +129,10 @@ int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_c
 
 /* Per-stage timing of plain and batched launches (not of graph replays), with
  * HIP events recorded on the launch stream around each kernel of the chain.
- * Stages, in order: bin, count, scan, tile (mesh + normals + local segments),
- * merge, flatten, scan roots, rank, final.  Enabling costs one event per kernel. */
-#define LIDAR_N_STAGES 9
+ * Stages, in order: bin, tile (numbering, mesh, normals, local segments),
+ * merge (segments across tiles), label (ranking and labels).  Enabling costs
+ * one event per kernel. */
+#define LIDAR_N_STAGES 4
 int lidar_ctx_set_profiling(lidar_ctx* ctx, int32_t enable);
 /* Waits for the profiled calls, then writes the summed milliseconds and the
  * number of timed launches of each stage (arrays of LIDAR_N_STAGES; launches

@@ -30,9 +30,13 @@ struct lidar_ctx {
 
     // device workspace
     uint64_t* keys = nullptr;
+    int32_t* forest = nullptr;    // same capacity as keys
     int64_t keys_cap = 0;
-    int32_t* tile_buf = nullptr;  // 6 arrays of tiles_cap
+    int32_t* tile_buf = nullptr;  // 2 int32 arrays of tiles_cap
+    uint64_t* stat_buf = nullptr; // 3 look-back status arrays of tiles_cap
+    int32_t* tickets = nullptr;   // 2 work-item counters
     int64_t tiles_cap = 0;
+    uint32_t epoch = 0;           // last epoch handed to a chain (0 is never used)
     int2* border = nullptr;
     int64_t border_cap = 0;
     char* d_table = nullptr;      // descriptor tables + elevations
@@ -43,11 +47,13 @@ struct lidar_ctx {
     int flip = 0;
 
     // captured batched chain
+    // Two instantiations of the same captured chain, launched alternately, so a
+    // launch never has to wait for the previous launch of the same executable.
     hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    int graph_next = 0;
     bool graph_valid = false;
     size_t graph_table_bytes = 0;
-    int graph_tiles_cap = 0, graph_pblk_cap = 0, graph_frames_cap = 0;
     int graph_tile_cells = 0;
 
     // tuning
@@ -86,20 +92,23 @@ struct lidar_ctx {
     Workspace workspace() const {
         Workspace ws;
         ws.keys = keys;
+        ws.forest = forest;
         ws.tile_v = tile_buf;
-        ws.tile_t = tile_buf + tiles_cap;
-        ws.tile_vbase = tile_buf + 2 * tiles_cap;
-        ws.tile_tbase = tile_buf + 3 * tiles_cap;
-        ws.tile_r = tile_buf + 4 * tiles_cap;
-        ws.tile_rbase = tile_buf + 5 * tiles_cap;
+        ws.tile_vbase = tile_buf + tiles_cap;
+        ws.stat_v = stat_buf;
+        ws.stat_t = stat_buf + tiles_cap;
+        ws.stat_r = stat_buf + 2 * tiles_cap;
+        ws.tickets = tickets;
         ws.border = border;
         ws.elev = reinterpret_cast<const double*>(d_table);
         return ws;
     }
     void drop_graph() {
-        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        for (auto& ge : graph_exec) {
+            if (ge) (void)hipGraphExecDestroy(ge);
+            ge = nullptr;
+        }
         if (graph) (void)hipGraphDestroy(graph);
-        graph_exec = nullptr;
         graph = nullptr;
         graph_valid = false;
     }
@@ -114,6 +123,10 @@ struct lidar_ctx {
     int wait_idle() {
         int rc = wait_buffer(0);
         return rc ? rc : wait_buffer(1);
+    }
+    uint32_t next_epoch() {
+        if (++epoch == 0) epoch = 1;
+        return epoch;
     }
 };
 
@@ -132,7 +145,7 @@ int validate_sensor(const lidar_sensor_t* sen, std::string& msg) {
     if (s < 1 || W % s != 0) { msg = "subsample must be >= 1 and divide n_azimuth"; return LIDAR_EINVAL; }
     if (sen->wrap != 0 && sen->wrap != 1) { msg = "wrap must be 0 or 1"; return LIDAR_EINVAL; }
     if (sen->wrap && W / s < 3) { msg = "a closed cylinder needs at least 3 sampled columns"; return LIDAR_EINVAL; }
-    if ((int64_t)H * (W / s) > (int64_t)1 << 30) { msg = "lattice too large"; return LIDAR_EINVAL; }
+    if ((int64_t)H * (W / s) > MAX_CELLS) { msg = "lattice too large (at most 2^29 cells)"; return LIDAR_EINVAL; }
     if (!sen->elev_rad) { msg = "elev_rad is NULL"; return LIDAR_EINVAL; }
     for (int i = 0; i < H; ++i) {
         if (!std::isfinite(sen->elev_rad[i])) { msg = "elevations must be finite"; return LIDAR_EINVAL; }
@@ -141,7 +154,7 @@ int validate_sensor(const lidar_sensor_t* sen, std::string& msg) {
             return LIDAR_EINVAL;
         }
     }
-    if (!std::isfinite(sen->az0_rad)) { msg = "az0_rad must be finite"; return LIDAR_EINVAL; }
+    if (!(std::fabs(sen->az0_rad) <= 2.0 * M_PI)) { msg = "az0_rad must lie in [-2 pi, 2 pi]"; return LIDAR_EINVAL; }
     return LIDAR_OK;
 }
 
@@ -196,7 +209,10 @@ void lidar_ctx_destroy(lidar_ctx* c) {
         for (auto ev : set) (void)hipEventDestroy(ev);
     for (auto ev : c->prof_free) (void)hipEventDestroy(ev);
     if (c->keys) (void)hipFree(c->keys);
+    if (c->forest) (void)hipFree(c->forest);
     if (c->tile_buf) (void)hipFree(c->tile_buf);
+    if (c->stat_buf) (void)hipFree(c->stat_buf);
+    if (c->tickets) (void)hipFree(c->tickets);
     if (c->border) (void)hipFree(c->border);
     if (c->d_table) (void)hipFree(c->d_table);
     for (int b = 0; b < 2; ++b) {
@@ -315,7 +331,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
 
     // ---- capacity ----
     const bool grow = cells > c->keys_cap || tiles > c->tiles_cap || border_slots > c->border_cap ||
-                      table_bytes > c->table_cap;
+                      table_bytes > c->table_cap || !c->tickets;
     if (grow) {
         int rc = c->wait_idle();
         if (rc) return rc;
@@ -323,9 +339,12 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         c->drop_graph();
         if (cells > c->keys_cap) {
             if (c->keys) (void)hipFree(c->keys);
+            if (c->forest) (void)hipFree(c->forest);
             c->keys = nullptr;
+            c->forest = nullptr;
             const int64_t cap = std::max<int64_t>(cells, c->keys_cap * 3 / 2);
-            if (hipMalloc(&c->keys, sizeof(uint64_t) * cap) != hipSuccess) {
+            if (hipMalloc(&c->keys, sizeof(uint64_t) * cap) != hipSuccess ||
+                hipMalloc(&c->forest, sizeof(int32_t) * cap) != hipSuccess) {
                 c->keys_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate the key grid");
             }
@@ -336,14 +355,22 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         }
         if (tiles > c->tiles_cap) {
             if (c->tile_buf) (void)hipFree(c->tile_buf);
+            if (c->stat_buf) (void)hipFree(c->stat_buf);
             c->tile_buf = nullptr;
+            c->stat_buf = nullptr;
             const int64_t cap = std::max<int64_t>(tiles, c->tiles_cap * 3 / 2);
-            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 6 * cap) != hipSuccess) {
+            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess ||
+                hipMalloc(&c->stat_buf, sizeof(uint64_t) * 3 * cap) != hipSuccess) {
                 c->tiles_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate tile arrays");
             }
+            // status words start at epoch 0, which no chain uses
+            e = hipMemsetAsync(c->stat_buf, 0, sizeof(uint64_t) * 3 * cap, stream);
+            if (e != hipSuccess) return c->hip_fail(e, "hipMemsetAsync");
             c->tiles_cap = cap;
         }
+        if (!c->tickets && hipMalloc(&c->tickets, sizeof(int32_t) * 2) != hipSuccess)
+            return c->fail(LIDAR_ENOMEM, "cannot allocate ticket counters");
         if (border_slots > c->border_cap) {
             if (c->border) (void)hipFree(c->border);
             c->border = nullptr;
@@ -420,6 +447,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             h->n_frames = 1;
             h->total_tiles = plan[f].n_tiles;
             h->total_pblk = plan[f].n_pblk;
+            h->epoch = c->next_epoch();
             FrameDesc* d = h->frames();
             const size_t elev_byte = off + sizeof(BatchHeader) + desc_bytes;
             // frames run one after another on the stream, so they share workspace offsets
@@ -433,7 +461,6 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.tile_cells = c->tile_cells;
             cfg.max_tiles = plan[f].n_tiles;
             cfg.max_pblk = plan[f].n_pblk;
-            cfg.max_frames = 1;
             cfg.grid = std::max(plan[f].n_tiles, plan[f].n_pblk);
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table + offs[f]), ws, cfg, stream, ev);
@@ -444,6 +471,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         h->n_frames = n_frames;
         h->total_tiles = (int)tiles;
         h->total_pblk = (int)pblk;
+        h->epoch = c->next_epoch();
         FrameDesc* d = h->frames();
         const size_t elev_base = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) / 8;
         int64_t cell_off = 0, border_off = 0;
@@ -465,7 +493,6 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.tile_cells = c->tile_cells;
             cfg.max_tiles = (int)tiles;
             cfg.max_pblk = (int)pblk;
-            cfg.max_frames = n_frames;
             cfg.grid = auto_grid;
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
@@ -485,20 +512,22 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 cfg.tile_cells = c->tile_cells;
                 cfg.max_tiles = (int)std::min<int64_t>(c->tiles_cap, INT32_MAX);
                 cfg.max_pblk = INT32_MAX;
-                cfg.max_frames = 1024;
                 cfg.grid = auto_grid;
                 hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
                 e = hipStreamEndCapture(cap_stream, &c->graph);
                 (void)hipStreamDestroy(cap_stream);
                 if (e2 != hipSuccess) return c->hip_fail(e2, "capture launch");
                 if (e != hipSuccess) return c->hip_fail(e, "hipStreamEndCapture");
-                e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
-                if (e != hipSuccess) { c->drop_graph(); return c->hip_fail(e, "hipGraphInstantiate"); }
+                for (auto& ge : c->graph_exec) {
+                    e = hipGraphInstantiate(&ge, c->graph, nullptr, nullptr, 0);
+                    if (e != hipSuccess) { c->drop_graph(); return c->hip_fail(e, "hipGraphInstantiate"); }
+                }
                 c->graph_valid = true;
                 c->graph_table_bytes = c->table_cap;
                 c->graph_tile_cells = c->tile_cells;
             }
-            e = hipGraphLaunch(c->graph_exec, stream);
+            e = hipGraphLaunch(c->graph_exec[c->graph_next], stream);
+            c->graph_next ^= 1;
             if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
         }
     }

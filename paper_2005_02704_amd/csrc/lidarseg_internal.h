@@ -8,7 +8,8 @@ namespace lidarseg {
 
 constexpr uint64_t KEY_EMPTY = ~0ull;
 constexpr int MAX_RINGS = 128;
-constexpr int POINT_BLOCK = 2048;  // points per binning work item
+constexpr int POINT_BLOCK = 1024;            // points per binning work item
+constexpr int64_t MAX_CELLS = 1ll << 29;     // per frame; keeps every count below 2^30
 
 // One frame of a batch, as the kernels see it.  Lives in device memory right
 // after a BatchHeader; all offsets index the context's workspace arrays.
@@ -36,7 +37,7 @@ struct BatchHeader {
     int32_t n_frames;
     int32_t total_tiles;
     int32_t total_pblk;
-    int32_t pad;
+    uint32_t epoch;           // distinguishes this chain's tile status words from older ones
     FrameDesc* frames() { return reinterpret_cast<FrameDesc*>(this + 1); }
 };
 static_assert(sizeof(BatchHeader) == 16, "header size");
@@ -47,11 +48,12 @@ static_assert(sizeof(FrameDesc) % 8 == 0, "desc alignment");
 struct Workspace {
     uint64_t* keys;       // (float(r^2) bits << 32) | point index; KEY_EMPTY = no point
     int32_t* tile_v;      // vertices owned by the tile
-    int32_t* tile_t;      // triangles anchored in the tile
     int32_t* tile_vbase;  // first vertex index of the tile (frame-local)
-    int32_t* tile_tbase;  // first triangle index of the tile
-    int32_t* tile_r;      // segment roots owned by the tile
-    int32_t* tile_rbase;  // rank of the tile's first root
+    uint64_t* stat_v;     // look-back status words: vertices, triangles, segment roots
+    uint64_t* stat_t;
+    uint64_t* stat_r;
+    int32_t* tickets;     // [2] work-item counters of the two look-back kernels
+    int32_t* forest;      // union-find parents per vertex, frame f at cell_off (V <= cells)
     int2* border;         // similar joins leaving a tile through its right edge
     const double* elev;   // ring elevations, per frame at elev_off
 };
@@ -62,16 +64,14 @@ inline int tile_width(int H, int tile_cells) {
     return tw < 1 ? 1 : tw;
 }
 
-// kernels (lidarseg_kernels.hip)
 struct LaunchCfg {
     int grid;        // workgroups for grid-stride stages (tiles / point blocks)
     int tile_cells;  // 512, 1024 or 2048
     int max_tiles;   // tiles in the largest batch this chain may see (for exact grids)
     int max_pblk;
-    int max_frames;
 };
 
-constexpr int N_STAGES = 9;  // bin, count, scan, tile, merge, flatten, scan roots, rank, final
+constexpr int N_STAGES = 4;  // bin, tile, merge, label
 
 // Enqueues the chain; when stage_events is non-null (N_STAGES + 1 events) an
 // event is recorded before the first kernel and after each kernel.

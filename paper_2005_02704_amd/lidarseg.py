@@ -30,8 +30,8 @@ LAUNCH = {"plain": LIDAR_LAUNCH_PLAIN, "batched": LIDAR_LAUNCH_BATCHED, "graph":
 EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lidar_last_error",
            "lidar_query_sizes", "lidar_mesh_segment", "lidar_ctx_set_tuning", "lidar_ctx_set_profiling",
            "lidar_ctx_stage_times")
-LIDAR_N_STAGES = 9
-STAGES = ("bin", "count", "scan", "tile", "merge", "flatten", "scan_roots", "rank", "final")
+LIDAR_N_STAGES = 4
+STAGES = ("bin", "tile", "merge", "label")
 
 
 class LidarError(RuntimeError):
@@ -159,6 +159,8 @@ class Outputs:
     def trimmed(self):
         """Views cut to the counts (synchronises with the device to read them)."""
         V, T, K = (int(x) for x in self.counts.cpu())
+        if V < 0 or T < 0 or K < 0:
+            raise LidarError(LIDAR_EDEVICE, "the frame's device work failed (counts = -1)")
         return dict(vertices=self.vertices[:V], normals=self.normals[:V], labels=self.labels[:V],
                     triangles=self.triangles[:T],
                     vertex_point=self.vertex_point[:V] if self.vertex_point is not None else None,

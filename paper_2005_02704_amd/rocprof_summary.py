@@ -1,0 +1,136 @@
+"""Condense rocprofv3 CSV output of a bench.py run into the text summaries kept
+in profiles/ (and the traffic JSON bench.py reads).
+
+Usage:
+  python -m paper_2005_02704_amd.rocprof_summary --trace DIR [--fetch DIR --write DIR]
+         --command "the rocprofv3 command" --out profiles/NAME.txt [--traffic-json FILE]
+
+The batched dispatches are those with the bench's fixed grid (grid_wg x 256
+threads); per-frame (plain) dispatches are summarised separately.  HBM bytes
+are FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
+counters read for the plain device copy bench.py --copy-calibration runs.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kname(s: str) -> str:
+    m = re.search(r"::(k_\w+)<", s)
+    if m:
+        return m.group(1)
+    return s.split("(")[0][:48]
+
+
+def _csv(d: str, suffix: str):
+    files = glob.glob(os.path.join(d, f"*{suffix}"))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("lidarseg_kernels.hip", "lidarseg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2005_02704_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def trace_summary(d: str, batched_grid: int):
+    rows = _csv(d, "kernel_trace.csv")
+    by = collections.defaultdict(list)
+    for r in rows:
+        g = int(r["Grid_Size_X"])
+        form = "batched" if g == batched_grid else "per-frame"
+        by[(kname(r["Kernel_Name"]), form)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return by
+
+
+def counter_summary(d: str, batched_grid: int):
+    rows = _csv(d, "counter_collection.csv")
+    by = collections.defaultdict(list)
+    copies = []
+    for r in rows:
+        name = kname(r["Kernel_Name"])
+        v = float(r["Counter_Value"])
+        if "copyBuffer" in name:
+            copies.append((int(r["Grid_Size"]), v))
+        elif int(r["Grid_Size"]) == batched_grid:
+            by[name].append(v)
+    # the calibration copy is the largest copy dispatch (the others stage inputs)
+    gmax = max(g for g, _ in copies)
+    return by, [v for g, v in copies if g == gmax]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--grid-wg", type=int, default=1024)
+    ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic-json")
+    ap.add_argument("--kernel", default="k_tile")
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--alg-bytes", type=float, default=0.0,
+                    help="algorithmic bytes per launch of --kernel (from bench.py's roofline)")
+    a = ap.parse_args()
+    grid = a.grid_wg * 256
+    lines = [f"# rocprofv3 summary: {a.kernel} and the rest of the chain, bench.py workload",
+             f"command: {a.command}", ""]
+    tr = trace_summary(a.trace, grid)
+    lines.append("kernel            form       calls   avg_us    min_us    total_us")
+    for (k, form), v in sorted(tr.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{k:<17} {form:<9} {len(v):6d} {sum(v) / len(v) / 1e3:9.2f} {min(v) / 1e3:9.2f} "
+                     f"{sum(v) / 1e3:11.1f}")
+    traffic = None
+    if a.fetch and a.write:
+        fb, fcopy = counter_summary(a.fetch, grid)
+        wb, wcopy = counter_summary(a.write, grid)
+        copy_kib = a.copy_mib * 1024.0
+        f_scale = copy_kib / (sum(fcopy) / len(fcopy))
+        w_scale = copy_kib / (sum(wcopy) / len(wcopy))
+        lines += ["", f"calibration: {a.copy_mib} MiB device copy reads FETCH_SIZE "
+                      f"{sum(fcopy) / len(fcopy):.1f} KiB, WRITE_SIZE {sum(wcopy) / len(wcopy):.1f} KiB "
+                      f"-> scale fetch x{f_scale:.3f}, write x{w_scale:.3f}",
+                  "kernel (batched)  fetch_MB  write_MB  hbm_MB (scaled)"]
+        for k in sorted(fb, key=lambda k: -sum(fb[k]) / len(fb[k])):
+            fm = sum(fb[k]) / len(fb[k]) * f_scale * 1024 / 1e6
+            wm = sum(wb.get(k, [0])) / max(1, len(wb.get(k, [0]))) * w_scale * 1024 / 1e6
+            lines.append(f"{k:<17} {fm:9.1f} {wm:9.1f} {fm + wm:9.1f}")
+            if k == a.kernel:
+                traffic = (fm + wm) * 1e6
+        if a.kernel in dict(tr) or (a.kernel, "batched") in tr:
+            v = tr[(a.kernel, "batched")]
+            avg_s = sum(v) / len(v) / 1e9
+            lines += ["", f"{a.kernel} batched: avg {avg_s * 1e6:.2f} us, HBM traffic {traffic / 1e6:.1f} MB "
+                          f"-> {traffic / avg_s / 1e9:.1f} GB/s"]
+            if a.alg_bytes:
+                lines.append(f"algorithmic bytes {a.alg_bytes / 1e6:.1f} MB -> "
+                             f"{a.alg_bytes / avg_s / 1e9:.1f} GB/s ({a.alg_bytes / avg_s / 8e12:.3f} of 8 TB/s)")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    if a.traffic_json and traffic is not None:
+        with open(a.traffic_json, "w") as f:
+            json.dump({"kernel": a.kernel, "hbm_bytes_per_launch": round(traffic),
+                       "kernel_source_hash": kernel_source_hash(), "frames": a.frames, "seed": a.seed,
+                       "command": a.command}, f, indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
