@@ -31,6 +31,9 @@ namespace lidarseg {
 namespace {
 
 constexpr int SPIN_LIMIT = 1 << 22;          // polls before a look-back gives up
+constexpr int WALK_LIMIT = 1 << 20;          // steps of any pointer walk (parents strictly
+                                             // decrease, so a walk is far shorter; the cap
+                                             // only guarantees that every loop ends)
 constexpr uint32_t POISON = (1u << 30) - 1;  // published prefix of a frame that failed
 constexpr double EL_GUARD = 1e-5;            // rad: FP32 elevation estimate decides outside this band
 constexpr float COL_GUARD = 0.02f;           // firings: FP32 firing estimate decides outside this band
@@ -256,17 +259,18 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
 // LDS union-find: links the larger root under the smaller (atomicMin), so every
 // root is the smallest cell of its tree.  Path halving only rewrites non-roots.
 __device__ __forceinline__ int lds_find(int* P, int x) {
-    while (true) {
+    for (int it = 0; it < WALK_LIMIT; ++it) {
         const int p = P[x];
         if (p == x) return x;
         const int gp = P[p];
         if (gp != p) P[x] = gp;
         x = gp;
     }
+    return x;
 }
 
 __device__ __forceinline__ void lds_union(int* P, int a, int b) {
-    while (true) {
+    for (int it = 0; it < WALK_LIMIT; ++it) {
         a = lds_find(P, a);
         b = lds_find(P, b);
         if (a == b) return;
@@ -666,7 +670,7 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
             const int vid = svid[l];
             if (vid < 0) continue;
             int r = l;
-            while (sparent[r] != r) r = sparent[r];
+            for (int it = 0; it < nown && sparent[r] != r; ++it) r = sparent[r];
             forest[vid] = svid[r];
         }
     }
@@ -679,17 +683,18 @@ __device__ __forceinline__ int g_load(const int* p) {
 }
 
 __device__ __forceinline__ int g_find(int* P, int x) {
-    while (true) {
+    for (int it = 0; it < WALK_LIMIT; ++it) {
         const int p = g_load(P + x);
         if (p == x) return x;
         const int gp = g_load(P + p);
         if (gp != p) __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x = gp;
     }
+    return x;
 }
 
 __device__ __forceinline__ void g_union(int* P, int a, int b) {
-    while (true) {
+    for (int it = 0; it < WALK_LIMIT; ++it) {
         a = g_find(P, a);
         b = g_find(P, b);
         if (a == b) return;
