@@ -48,7 +48,7 @@ def stage_bytes(stage, N, V, T):
         return 12 * V + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T  # kept xyz in; vertices,
         # normals, vertex_point, local labels, triangles out
     if stage == "label":
-        return 8 * V                          # forest entry read + label written
+        return 8 * V                          # segment root read + label written
     return 0
 
 

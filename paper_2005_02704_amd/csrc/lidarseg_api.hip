@@ -32,11 +32,12 @@ struct lidar_ctx {
     uint64_t* keys = nullptr;
     int32_t* forest = nullptr;    // same capacity as keys
     int64_t keys_cap = 0;
-    int32_t* tile_buf = nullptr;  // 2 int32 arrays of tiles_cap
-    uint64_t* stat_buf = nullptr; // 3 look-back status arrays of tiles_cap
-    int32_t* tickets = nullptr;   // 2 work-item counters
+    int32_t* tile_buf = nullptr;  // 2 int32 arrays of tiles_cap: vertices, triangles per tile
     int64_t tiles_cap = 0;
-    uint32_t epoch = 0;           // last epoch handed to a chain (0 is never used)
+    uint64_t* rootbits = nullptr; // VITEM_WORDS per labelling item
+    uint32_t* wprefix = nullptr;  // VITEM_WORDS per labelling item
+    int32_t* vitem_roots = nullptr;  // one per labelling item
+    int64_t vitems_cap = 0;
     int2* border = nullptr;
     int64_t border_cap = 0;
     char* d_table = nullptr;      // descriptor tables + elevations
@@ -94,11 +95,10 @@ struct lidar_ctx {
         ws.keys = keys;
         ws.forest = forest;
         ws.tile_v = tile_buf;
-        ws.tile_vbase = tile_buf + tiles_cap;
-        ws.stat_v = stat_buf;
-        ws.stat_t = stat_buf + tiles_cap;
-        ws.stat_r = stat_buf + 2 * tiles_cap;
-        ws.tickets = tickets;
+        ws.tile_t = tile_buf + tiles_cap;
+        ws.rootbits = rootbits;
+        ws.wprefix = wprefix;
+        ws.vitem_roots = vitem_roots;
         ws.border = border;
         ws.elev = reinterpret_cast<const double*>(d_table);
         return ws;
@@ -124,16 +124,12 @@ struct lidar_ctx {
         int rc = wait_buffer(0);
         return rc ? rc : wait_buffer(1);
     }
-    uint32_t next_epoch() {
-        if (++epoch == 0) epoch = 1;
-        return epoch;
-    }
 };
 
 namespace {
 
 struct FramePlan {
-    int H, W, s, Wp, wrap, TW, n_tiles, n_pblk;
+    int H, W, s, Wp, wrap, TW, n_tiles, n_pblk, n_vitem;
     int64_t cells, border_slots;
 };
 
@@ -211,8 +207,9 @@ void lidar_ctx_destroy(lidar_ctx* c) {
     if (c->keys) (void)hipFree(c->keys);
     if (c->forest) (void)hipFree(c->forest);
     if (c->tile_buf) (void)hipFree(c->tile_buf);
-    if (c->stat_buf) (void)hipFree(c->stat_buf);
-    if (c->tickets) (void)hipFree(c->tickets);
+    if (c->rootbits) (void)hipFree(c->rootbits);
+    if (c->wprefix) (void)hipFree(c->wprefix);
+    if (c->vitem_roots) (void)hipFree(c->vitem_roots);
     if (c->border) (void)hipFree(c->border);
     if (c->d_table) (void)hipFree(c->d_table);
     for (int b = 0; b < 2; ++b) {
@@ -282,7 +279,8 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     // ---- plan ----
     std::vector<FramePlan> plan(n_frames);
     int64_t cells = 0, border_slots = 0, elev_total = 0;
-    int64_t tiles = 0, pblk = 0;
+    int64_t tiles = 0, pblk = 0, vitems = 0;
+    int64_t max_cells = 0, max_tiles_f = 0, max_pblk_f = 0, max_vitem_f = 0, max_border_f = 0;
     for (int f = 0; f < n_frames; ++f) {
         const lidar_frame_t& fr = frames[f];
         std::string msg;
@@ -305,14 +303,29 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         p.n_tiles = (p.Wp + p.TW - 1) / p.TW;
         p.n_pblk = (int)((fr.n_points + POINT_BLOCK - 1) / POINT_BLOCK);
         p.cells = (int64_t)p.H * p.Wp;
+        p.n_vitem = (int)((p.cells + VITEM - 1) / VITEM);
         p.border_slots = (int64_t)p.n_tiles * 2 * p.H;
         cells += p.cells;
         border_slots += p.border_slots;
         elev_total += p.H;
         tiles += p.n_tiles;
         pblk += p.n_pblk;
+        vitems += p.n_vitem;
+        max_cells = std::max(max_cells, p.cells);
+        max_tiles_f = std::max<int64_t>(max_tiles_f, p.n_tiles);
+        max_pblk_f = std::max<int64_t>(max_pblk_f, p.n_pblk);
+        max_vitem_f = std::max<int64_t>(max_vitem_f, p.n_vitem);
+        max_border_f = std::max(max_border_f, p.border_slots);
     }
-    if (tiles > INT32_MAX || pblk > INT32_MAX) return c->fail(LIDAR_EINVAL, "batch too large");
+    if (tiles > INT32_MAX || pblk > INT32_MAX || cells > MAX_BATCH_CELLS || border_slots > INT32_MAX)
+        return c->fail(LIDAR_EINVAL, "batch too large (at most 2^31 - 1024 lattice cells in one call)");
+    // plain launches run the frames one after another on shared workspace offsets
+    if (launch == LIDAR_LAUNCH_PLAIN) {
+        cells = max_cells;
+        tiles = max_tiles_f;
+        vitems = max_vitem_f;
+        border_slots = max_border_f;
+    }
 
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
@@ -330,8 +343,8 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     }
 
     // ---- capacity ----
-    const bool grow = cells > c->keys_cap || tiles > c->tiles_cap || border_slots > c->border_cap ||
-                      table_bytes > c->table_cap || !c->tickets;
+    const bool grow = cells > c->keys_cap || tiles > c->tiles_cap || vitems > c->vitems_cap ||
+                      border_slots > c->border_cap || table_bytes > c->table_cap;
     if (grow) {
         int rc = c->wait_idle();
         if (rc) return rc;
@@ -355,22 +368,30 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         }
         if (tiles > c->tiles_cap) {
             if (c->tile_buf) (void)hipFree(c->tile_buf);
-            if (c->stat_buf) (void)hipFree(c->stat_buf);
             c->tile_buf = nullptr;
-            c->stat_buf = nullptr;
             const int64_t cap = std::max<int64_t>(tiles, c->tiles_cap * 3 / 2);
-            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess ||
-                hipMalloc(&c->stat_buf, sizeof(uint64_t) * 3 * cap) != hipSuccess) {
+            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess) {
                 c->tiles_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate tile arrays");
             }
-            // status words start at epoch 0, which no chain uses
-            e = hipMemsetAsync(c->stat_buf, 0, sizeof(uint64_t) * 3 * cap, stream);
-            if (e != hipSuccess) return c->hip_fail(e, "hipMemsetAsync");
             c->tiles_cap = cap;
         }
-        if (!c->tickets && hipMalloc(&c->tickets, sizeof(int32_t) * 2) != hipSuccess)
-            return c->fail(LIDAR_ENOMEM, "cannot allocate ticket counters");
+        if (vitems > c->vitems_cap) {
+            if (c->rootbits) (void)hipFree(c->rootbits);
+            if (c->wprefix) (void)hipFree(c->wprefix);
+            if (c->vitem_roots) (void)hipFree(c->vitem_roots);
+            c->rootbits = nullptr;
+            c->wprefix = nullptr;
+            c->vitem_roots = nullptr;
+            const int64_t cap = std::max<int64_t>(vitems, c->vitems_cap * 3 / 2);
+            if (hipMalloc(&c->rootbits, sizeof(uint64_t) * VITEM_WORDS * cap) != hipSuccess ||
+                hipMalloc(&c->wprefix, sizeof(uint32_t) * VITEM_WORDS * cap) != hipSuccess ||
+                hipMalloc(&c->vitem_roots, sizeof(int32_t) * cap) != hipSuccess) {
+                c->vitems_cap = 0;
+                return c->fail(LIDAR_ENOMEM, "cannot allocate labelling arrays");
+            }
+            c->vitems_cap = cap;
+        }
         if (border_slots > c->border_cap) {
             if (c->border) (void)hipFree(c->border);
             c->border = nullptr;
@@ -407,8 +428,8 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     }
     char* const htab = c->h_table[buf];
     std::memset(htab, 0, table_bytes);
-    auto fill_desc = [&](FrameDesc& d, int f, int64_t cell_off, int64_t border_off, int tile_off,
-                         int pblk_off, int elev_off) {
+    auto fill_desc = [&](FrameDesc& d, int f, int64_t cell_off, int64_t border_off, int tile_off, int pblk_off,
+                         int vitem_off, int elev_off) {
         const lidar_frame_t& fr = frames[f];
         const lidar_result_t& r = results[f];
         const FramePlan& p = plan[f];
@@ -426,6 +447,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         d.H = p.H; d.W = p.W; d.s = p.s; d.Wp = p.Wp; d.wrap = p.wrap; d.TW = p.TW;
         d.n_tiles = p.n_tiles; d.tile_off = tile_off;
         d.n_pblk = p.n_pblk; d.pblk_off = pblk_off;
+        d.n_vitem = p.n_vitem; d.vitem_off = vitem_off;
         d.elev_off = elev_off;
         d.az0 = fr.sensor->az0_rad;
         d.dphi = 2.0 * M_PI / (double)p.W;
@@ -447,11 +469,12 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             h->n_frames = 1;
             h->total_tiles = plan[f].n_tiles;
             h->total_pblk = plan[f].n_pblk;
-            h->epoch = c->next_epoch();
+            h->total_vitems = plan[f].n_vitem;
+            h->total_border = (int)plan[f].border_slots;
             FrameDesc* d = h->frames();
             const size_t elev_byte = off + sizeof(BatchHeader) + desc_bytes;
             // frames run one after another on the stream, so they share workspace offsets
-            fill_desc(*d, f, 0, 0, 0, 0, (int)(elev_byte / 8));
+            fill_desc(*d, f, 0, 0, 0, 0, 0, (int)(elev_byte / 8));
             off += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
         }
         e = hipMemcpyAsync(c->d_table, htab, table_bytes, hipMemcpyHostToDevice, stream);
@@ -461,7 +484,10 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.tile_cells = c->tile_cells;
             cfg.max_tiles = plan[f].n_tiles;
             cfg.max_pblk = plan[f].n_pblk;
-            cfg.grid = std::max(plan[f].n_tiles, plan[f].n_pblk);
+            cfg.max_vitems = plan[f].n_vitem;
+            cfg.max_border = (int)plan[f].border_slots;
+            cfg.max_frames = 1;
+            cfg.grid = std::max(std::max(plan[f].n_tiles, plan[f].n_pblk), plan[f].n_vitem);
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table + offs[f]), ws, cfg, stream, ev);
             if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
@@ -471,17 +497,19 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         h->n_frames = n_frames;
         h->total_tiles = (int)tiles;
         h->total_pblk = (int)pblk;
-        h->epoch = c->next_epoch();
+        h->total_vitems = (int)vitems;
+        h->total_border = (int)border_slots;
         FrameDesc* d = h->frames();
         const size_t elev_base = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) / 8;
         int64_t cell_off = 0, border_off = 0;
-        int tile_off = 0, pblk_off = 0, elev_off = (int)elev_base;
+        int tile_off = 0, pblk_off = 0, vitem_off = 0, elev_off = (int)elev_base;
         for (int f = 0; f < n_frames; ++f) {
-            fill_desc(d[f], f, cell_off, border_off, tile_off, pblk_off, elev_off);
+            fill_desc(d[f], f, cell_off, border_off, tile_off, pblk_off, vitem_off, elev_off);
             cell_off += plan[f].cells;
             border_off += plan[f].border_slots;
             tile_off += plan[f].n_tiles;
             pblk_off += plan[f].n_pblk;
+            vitem_off += plan[f].n_vitem;
             elev_off += plan[f].H;
         }
         // the device table is read only by this call's kernels, which run after
@@ -493,6 +521,9 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.tile_cells = c->tile_cells;
             cfg.max_tiles = (int)tiles;
             cfg.max_pblk = (int)pblk;
+            cfg.max_vitems = (int)vitems;
+            cfg.max_border = (int)border_slots;
+            cfg.max_frames = n_frames;
             cfg.grid = auto_grid;
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
@@ -512,6 +543,9 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 cfg.tile_cells = c->tile_cells;
                 cfg.max_tiles = (int)std::min<int64_t>(c->tiles_cap, INT32_MAX);
                 cfg.max_pblk = INT32_MAX;
+                cfg.max_vitems = (int)std::min<int64_t>(c->vitems_cap, INT32_MAX);
+                cfg.max_border = (int)std::min<int64_t>(c->border_cap, INT32_MAX);
+                cfg.max_frames = INT32_MAX;
                 cfg.grid = auto_grid;
                 hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
                 e = hipStreamEndCapture(cap_stream, &c->graph);

@@ -9,7 +9,10 @@ namespace lidarseg {
 constexpr uint64_t KEY_EMPTY = ~0ull;
 constexpr int MAX_RINGS = 128;
 constexpr int POINT_BLOCK = 1024;            // points per binning work item
+constexpr int VITEM = 1024;                  // vertex slots per labelling work item
+constexpr int VITEM_WORDS = VITEM / 64;      // 64-bit root-flag words per labelling item
 constexpr int64_t MAX_CELLS = 1ll << 29;     // per frame; keeps every count below 2^30
+constexpr int64_t MAX_BATCH_CELLS = (1ll << 31) - VITEM;  // forest positions are int32
 
 // One frame of a batch, as the kernels see it.  Lives in device memory right
 // after a BatchHeader; all offsets index the context's workspace arrays.
@@ -23,11 +26,12 @@ struct FrameDesc {
     int32_t* vpoint;          // may be null
     int64_t* counts;
     int64_t n_points;
-    int64_t cell_off;         // first cell of this frame in the key grid
-    int64_t border_off;       // first border slot (int2) of this frame
+    int64_t cell_off;         // first cell of this frame in the key grid and the forest
+    int64_t border_off;       // first border slot (int2) of this frame: 2H slots per tile
     int32_t H, W, s, Wp, wrap, TW;
     int32_t n_tiles, tile_off;
     int32_t n_pblk, pblk_off;
+    int32_t n_vitem, vitem_off;  // labelling items (VITEM vertex slots each); words at vitem_off * VITEM_WORDS
     int32_t elev_off, pad0;
     double az0, dphi, rmin2, rmax2;
     double thr[3];
@@ -37,24 +41,28 @@ struct BatchHeader {
     int32_t n_frames;
     int32_t total_tiles;
     int32_t total_pblk;
-    uint32_t epoch;           // distinguishes this chain's tile status words from older ones
+    int32_t total_vitems;
+    int32_t total_border;     // border slots of the batch
+    int32_t pad;
     FrameDesc* frames() { return reinterpret_cast<FrameDesc*>(this + 1); }
 };
-static_assert(sizeof(BatchHeader) == 16, "header size");
+static_assert(sizeof(BatchHeader) == 24, "header size");
 static_assert(sizeof(FrameDesc) % 8 == 0, "desc alignment");
 
 // Device workspace of a context.  Per-tile arrays are indexed by the batch-wide
-// tile index; keys by cell_off + k*H + i (firing order within a frame).
+// tile index; keys and forest by cell_off + cell (firing order within a frame),
+// the forest's entries being batch-wide positions cell_off + vertex.
 struct Workspace {
     uint64_t* keys;       // (float(r^2) bits << 32) | point index; KEY_EMPTY = no point
-    int32_t* tile_v;      // vertices owned by the tile
-    int32_t* tile_vbase;  // first vertex index of the tile (frame-local)
-    uint64_t* stat_v;     // look-back status words: vertices, triangles, segment roots
-    uint64_t* stat_t;
-    uint64_t* stat_r;
-    int32_t* tickets;     // [2] work-item counters of the two look-back kernels
-    int32_t* forest;      // union-find parents per vertex, frame f at cell_off (V <= cells)
-    int2* border;         // similar joins leaving a tile through its right edge
+    int32_t* forest;      // union-find parent of each vertex, as a batch-wide position
+    int32_t* tile_v;      // vertices owned by each tile
+    int32_t* tile_t;      // triangles anchored in each tile
+    uint64_t* rootbits;   // per 64 vertex slots: which vertices are segment roots
+    uint32_t* wprefix;    // per 64 vertex slots: roots of its labelling item before the word
+    int32_t* vitem_roots; // per labelling item: its roots, then (after k_scan) the roots
+                          // of the frame before it
+    int2* border;         // per tile and ring: the similar C and B joins that leave the
+                          // tile through its right edge (forest positions), or (-1, -1)
     const double* elev;   // ring elevations, per frame at elev_off
 };
 
@@ -65,13 +73,16 @@ inline int tile_width(int H, int tile_cells) {
 }
 
 struct LaunchCfg {
-    int grid;        // workgroups for grid-stride stages (tiles / point blocks)
+    int grid;        // workgroups for grid-stride stages
     int tile_cells;  // 512, 1024 or 2048
     int max_tiles;   // tiles in the largest batch this chain may see (for exact grids)
     int max_pblk;
+    int max_vitems;
+    int max_border;  // border slots
+    int max_frames;
 };
 
-constexpr int N_STAGES = 4;  // bin, tile, merge, label
+constexpr int N_STAGES = 7;  // bin, count, tile, merge, flatten, scan, label
 
 // Enqueues the chain; when stage_events is non-null (N_STAGES + 1 events) an
 // event is recorded before the first kernel and after each kernel.

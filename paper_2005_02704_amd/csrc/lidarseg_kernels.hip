@@ -1,18 +1,22 @@
 // HIP kernels for gfx950 (MI355X): bin -> sub-sample -> mesh -> normals -> labels.
 //
-// One batch of frames runs as a chain of four grid-stride kernels; each kernel
-// walks its work items (point blocks or lattice tiles) across every frame of the
-// batch, reading the per-frame descriptors from device memory, so the same
-// launches (and the same captured graph) serve any batch that fits the workspace.
+// One batch of frames runs as a chain of seven grid-stride kernels; each kernel
+// walks its work items (point blocks, lattice tiles, border slots, blocks of
+// vertex slots or frames) across every frame of the batch, reading the
+// per-frame descriptors from device memory, so the same launches (and the same
+// captured graph) serve any batch that fits the workspace.  No kernel waits for
+// another workgroup, and no work item is handed out through a shared counter.
 //
 // Stage map (Mukherjee et al., PReMI 2019, Section 2):
-//   k_bin           points -> (ring, firing) cell, sub-sampling, nearest return   [opening paragraph]
-//   k_tile          per tile in LDS: gather, vertex + triangle numbering (single
-//                   pass: decoupled look-back over tiles), mesh triangles, normals,
-//                   similarity of joins, local union-find       [Mesh Construction, Normal Estimation, Algorithm 1]
-//   k_merge         unions across tile borders and the azimuth seam               [Algorithm 1]
-//   k_label         segment roots ranked in firing order (single pass, look-back
-//                   over tiles); every vertex takes its root's label; key cells reset
+//   k_bin      points -> (ring, firing) cell, sub-sampling, nearest return     [opening paragraph]
+//   k_count    vertices and triangles owned by each tile                       [Mesh Construction]
+//   k_tile     per tile in LDS: vertex and triangle numbering, mesh triangles,
+//              normals, similarity of joins, local segments                   [Mesh Construction,
+//                                                                               Normal Estimation, Algorithm 1]
+//   k_merge    unions of the similar joins that cross tile borders             [Algorithm 1]
+//   k_flatten  every vertex to its segment root; roots flagged; key cells reset
+//   k_scan     per frame: roots before each 64-vertex word (their rank base)
+//   k_resolve  label = 1 + rank of the vertex's root
 //
 // Algorithm 1 floods through neighbours whose normal components differ by less
 // than the thresholds; that test is symmetric, so the flood's label classes are
@@ -20,24 +24,19 @@
 // first vertex in the visiting order gives the same labels.  Union-find here
 // always links the larger root under the smaller, so a root is the smallest
 // vertex of its segment and the labels follow from ranking the roots.
-//
-// The two look-back kernels (k_tile, k_label) take tiles from an atomic ticket counter, so a tile
-// only ever waits for tiles taken earlier by workgroups that are already running;
-// the waits are bounded (SPIN_LIMIT) and a frame whose wait runs out reports
-// counts of -1 instead of hanging.
 #include "lidarseg_internal.h"
 
 namespace lidarseg {
 namespace {
 
-constexpr int SPIN_LIMIT = 1 << 22;          // polls before a look-back gives up
 constexpr int WALK_LIMIT = 1 << 20;          // steps of any pointer walk (parents strictly
                                              // decrease, so a walk is far shorter; the cap
                                              // only guarantees that every loop ends)
-constexpr uint32_t POISON = (1u << 30) - 1;  // published prefix of a frame that failed
 constexpr double EL_GUARD = 1e-5;            // rad: FP32 elevation estimate decides outside this band
 constexpr float COL_GUARD = 0.02f;           // firings: FP32 firing estimate decides outside this band
 constexpr int COL_GUARD_MAX_W = 16384;       // wider sweeps always decide the firing in FP64
+constexpr double LEN2_FLOOR = 1e-300;        // added to squared edge lengths: an absent edge
+                                             // (zero vector) gets a tiny positive length
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -63,74 +62,20 @@ __device__ __forceinline__ bool occupied(uint64_t key, int64_t n_points) {
     return key != KEY_EMPTY && (int64_t)(uint32_t)key < n_points;
 }
 
-// Largest frame f with F[f].tile_off <= t.
-__device__ __forceinline__ int frame_of_tile(const FrameDesc* F, int nf, int t) {
+// Largest frame f with F[f].*off <= x (offsets ascend with f).
+template <int32_t FrameDesc::*OFF>
+__device__ __forceinline__ int frame_of(const FrameDesc* F, int nf, int x) {
     int lo = 0, hi = nf - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (F[mid].tile_off <= t) lo = mid; else hi = mid - 1;
+        if (F[mid].*OFF <= x) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-__device__ __forceinline__ int frame_of_pblk(const FrameDesc* F, int nf, int b) {
-    int lo = 0, hi = nf - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (F[mid].pblk_off <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// ---------------------------------------------------------------------------
-// Tile status words for the look-back: [epoch:32 | flag:2 | value:30].
-// flag 1 = the tile's own count, 2 = inclusive prefix of its frame up to it.
-__device__ __forceinline__ uint64_t st_pack(uint32_t epoch, uint32_t flag, uint32_t value) {
-    return ((uint64_t)epoch << 32) | ((uint64_t)flag << 30) | (uint64_t)value;
-}
-
-__device__ __forceinline__ void st_store(uint64_t* p, uint64_t w) {
-    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t st_load(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Exclusive prefix over tiles [first, t) of the values published in st[],
-// computed by one wave that inspects 64 predecessors at a time.  Returns -1 if
-// a predecessor stayed silent for SPIN_LIMIT polls.
-__device__ int lookback(const uint64_t* st, int t, int first, uint32_t epoch) {
-    const int lane = lane_id();
-    int acc = 0;
-    int j = t - 1;
-    int spins = 0;
-    while (j >= first) {
-        const int idx = j - lane;
-        uint32_t flag = 2u, val = 0u;            // lanes past the frame's first tile: prefix 0
-        if (idx >= first) {
-            const uint64_t w = st_load(st + idx);
-            if ((uint32_t)(w >> 32) == epoch) {
-                flag = (uint32_t)(w >> 30) & 3u;
-                val = (uint32_t)w & POISON;
-            } else {
-                flag = 0u;
-            }
-        }
-        const uint64_t inc = __ballot(flag == 2u);
-        const uint64_t avail = __ballot(flag != 0u);
-        const int k = inc ? __builtin_ctzll(inc) : 64;          // nearest inclusive lane
-        const uint64_t need = (k >= 63) ? ~0ull : ((2ull << k) - 1ull);
-        if ((avail & need) != need) {
-            if (++spins > SPIN_LIMIT) return -1;
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        acc += wave_sum(lane <= k ? (int)val : 0);
-        if (k < 64) break;
-        j -= 64;
-    }
-    return acc;
+// x / H for the small non-negative LDS indices used here (x < 2^13, H <= 128).
+__device__ __forceinline__ int div_small(int x, float inv_h) {
+    return (int)(((float)x + 0.5f) * inv_h);
 }
 
 // Nearest ring elevation, ties to the upper (lower-index) ring.  e is strictly
@@ -174,16 +119,12 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
     constexpr int PPT = POINT_BLOCK / NT;  // points per thread per item
     __shared__ double s_elev[MAX_RINGS];
     __shared__ double s_mid[MAX_RINGS];    // s_mid[i]: midpoint of rings i and i+1
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ws.tickets[0] = 0;
-        ws.tickets[1] = 0;
-    }
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
     const int nb = hdr->total_pblk;
     int cur = -1;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        const int f = frame_of_pblk(F, nf, b);
+        const int f = frame_of<&FrameDesc::pblk_off>(F, nf, b);
         const FrameDesc* fd = F + f;
         const int H = fd->H;
         if (f != cur) {
@@ -256,6 +197,81 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
 }
 
 // ---------------------------------------------------------------------------
+// Vertices and triangles owned by each tile (from the key grid alone), so that
+// k_tile can number its vertices and triangles without waiting on other tiles.
+// A vertex is an occupied cell; own anchor (i, k) with i+1 < H has triangle
+// T_a = (p, A, B) and T_b = (p, B, C) when all three corners are occupied.
+template <int NT, int MAXC>
+__global__ __launch_bounds__(NT) void k_count(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int NO = MAXC + MAX_RINGS;      // own cells + right column
+    constexpr int RO = (NO + NT - 1) / NT;
+    constexpr int NW = NT / 64;
+    __shared__ uint8_t socc[NO];
+    __shared__ int s_red[2][NW];
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
+        const int H = fd->H, Wp = fd->Wp;
+        const float inv_h = 1.0f / (float)H;
+        const int k0 = (t - fd->tile_off) * fd->TW;
+        const int TWe = min(fd->TW, Wp - k0);
+        const int nown = H * TWe;
+        const bool inside = k0 + TWe < Wp;
+        const bool right = inside || fd->wrap;
+        const int64_t rbase = (int64_t)(inside ? k0 + TWe : 0) * H;
+        const uint64_t* keys = ws.keys + fd->cell_off;
+        const int64_t np = fd->n_points;
+        __syncthreads();  // the previous tile's readers are done
+        uint64_t key[RO];
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            key[r] = KEY_EMPTY;
+            if (l < nown) key[r] = keys[(int64_t)k0 * H + l];
+            else if (l < nown + H && right) key[r] = keys[rbase + (l - nown)];
+        }
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l < nown + H) socc[l] = occupied(key[r], np) ? 1 : 0;
+        }
+        __syncthreads();
+        int nv = 0, nt = 0;
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l < nown && socc[l]) {
+                ++nv;
+                const int i = l - div_small(l, inv_h) * H;
+                if (i + 1 < H) {
+                    const int a = socc[l + 1], b = socc[l + H + 1], c = socc[l + H];
+                    nt += (a & b) + (b & c);
+                }
+            }
+        }
+        nv = wave_sum(nv);
+        nt = wave_sum(nt);
+        if (lane == 0) {
+            s_red[0][wv] = nv;
+            s_red[1][wv] = nt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int sv = 0, st = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                sv += s_red[0][w];
+                st += s_red[1][w];
+            }
+            ws.tile_v[t] = sv;
+            ws.tile_t[t] = st;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS union-find: links the larger root under the smaller (atomicMin), so every
 // root is the smallest cell of its tree.  Path halving only rewrites non-roots.
 __device__ __forceinline__ int lds_find(int* P, int x) {
@@ -281,18 +297,19 @@ __device__ __forceinline__ void lds_union(int* P, int a, int b) {
     }
 }
 
-__device__ __forceinline__ bool similar(float ax, float ay, float az, float bx, float by, float bz,
-                                        double tx, double ty, double tz) {
-    const bool ha = !(ax == 0.0f && ay == 0.0f && az == 0.0f);
-    const bool hb = !(bx == 0.0f && by == 0.0f && bz == 0.0f);
-    // differences of two floats are exact in FP64
-    return ha && hb && fabs((double)ax - (double)bx) < tx && fabs((double)ay - (double)by) < ty &&
-           fabs((double)az - (double)bz) < tz;
+// Algorithm 1's test: both vertices have normals and every component differs by
+// strictly less than its threshold.  Differences of two floats are exact in FP64.
+__device__ __forceinline__ bool similar(float4 a, float4 b, double tx, double ty, double tz) {
+    const bool ha = !(a.x == 0.0f && a.y == 0.0f && a.z == 0.0f);
+    const bool hb = !(b.x == 0.0f && b.y == 0.0f && b.z == 0.0f);
+    return ha && hb && fabs((double)a.x - (double)b.x) < tx && fabs((double)a.y - (double)b.y) < ty &&
+           fabs((double)a.z - (double)b.z) < tz;
 }
 
-// FP64 reciprocal and reciprocal square root: the hardware estimate (about 2^-26
-// relative error) plus one Newton step (about 2^-50).  Weights and the final
-// scaling need no correctly rounded division: the normal is rounded to FP32.
+// FP64 reciprocal, reciprocal square root and square root: the hardware estimate
+// (about 2^-23 relative error) plus one Newton step (about 2^-46).  Weights and
+// the final scaling need no correctly rounded division: the normal is rounded
+// to FP32.
 __device__ __forceinline__ double rcp_dp(double x) {
     const double y = __builtin_amdgcn_rcp(x);
     return fma(y, fma(-x, y, 1.0), y);
@@ -303,58 +320,56 @@ __device__ __forceinline__ double rsq_dp(double x) {
     return fma(y, fma(-0.5 * x * y, y, 0.5), y);
 }
 
-// x / H for the small non-negative LDS indices used here (x < 2^13, H <= 128).
-__device__ __forceinline__ int div_small(int x, float inv_h) {
-    return (int)(((float)x + 0.5f) * inv_h);
+__device__ __forceinline__ double sqrt_dp(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double s = x * y;
+    return fma(fma(-s, s, x), 0.5 * y, s);
 }
 
 // Weighted normal of LDS cell lx (ring i): sum over cycle-adjacent present pairs
 // (A,B),(B,C),(C,D),(D,E),(E,F),(F,A) of (V_t x V_u) / (|V_t| + |V_u|), scaled to
-// unit length (Section 2, Normal Estimation).  Edge vectors are exact in FP64;
-// empty cells hold NaN coordinates.  Branch-free: an absent neighbour reads the
-// cell itself and contributes zero.  Neighbours are visited once, in cycle order,
-// keeping only the previous and the first edge vector live.
-__device__ __forceinline__ void edge_vec(const float* sx, const float* sy, const float* sz, int q, bool ok,
-                                         double px, double py, double pz, double& vx, double& vy,
-                                         double& vz, double& len, bool& pres) {
-    const float qx = sx[q], qy = sy[q], qz = sz[q];
-    pres = ok && (qx == qx);
-    vx = pres ? (double)qx - px : 0.0;
-    vy = pres ? (double)qy - py : 0.0;
-    vz = pres ? (double)qz - pz : 0.0;
-    const double l2 = vx * vx + vy * vy + vz * vz;
-    len = pres ? l2 * rsq_dp(l2) : 1.0;
-}
-
-__device__ __forceinline__ void vertex_normal(const float* sx, const float* sy, const float* sz,
-                                              int lx, int i, int H, float& onx, float& ony, float& onz) {
+// unit length (Section 2, Normal Estimation).  Edge vectors are exact in FP64.
+// Branch-free: an absent neighbour (off the ring range, or an empty cell, whose
+// coordinates are NaN) is replaced by the vertex itself, so its edge vector is
+// zero, its cross products vanish and its length is a tiny positive number.
+// Neighbours are visited once, in cycle order, keeping only the previous and the
+// first edge vector live.
+__device__ __forceinline__ void vertex_normal(const float4* sc, int lx, int i, int H, float& onx, float& ony,
+                                              float& onz) {
     const bool up = i >= 1, dn = i + 1 < H;
-    const int q[6] = {dn ? lx + 1 : lx, dn ? lx + H + 1 : lx, lx + H,
-                      up ? lx - 1 : lx, up ? lx - H - 1 : lx, lx - H};
-    const bool ok[6] = {dn, dn, true, up, up, true};
-    const double px = sx[lx], py = sy[lx], pz = sz[lx];
-    double v0x, v0y, v0z, l0;
-    bool p0;
-    edge_vec(sx, sy, sz, q[0], ok[0], px, py, pz, v0x, v0y, v0z, l0, p0);
-    double ux = v0x, uy = v0y, uz = v0z, lu = l0;
-    bool pu = p0;
+    const int off[6] = {1, H + 1, H, -1, -H - 1, -H};
+    const bool inr[6] = {dn, dn, true, up, up, true};
+    const float4 P = sc[lx];
+    const double px = P.x, py = P.y, pz = P.z;
+    double fx = 0.0, fy = 0.0, fz = 0.0, lf = 0.0;
+    bool pf = false;
+    double ux = 0.0, uy = 0.0, uz = 0.0, lu = 0.0;
+    bool pu = false;
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool any = false;
 #pragma unroll
-    for (int t = 1; t <= 6; ++t) {
+    for (int t = 0; t <= 6; ++t) {
         double vx, vy, vz, lv;
         bool pv;
         if (t < 6) {
-            edge_vec(sx, sy, sz, q[t], ok[t], px, py, pz, vx, vy, vz, lv, pv);
+            const float4 Q = sc[inr[t] ? lx + off[t] : lx];
+            pv = inr[t] && (Q.x == Q.x);
+            vx = (double)(pv ? Q.x : P.x) - px;
+            vy = (double)(pv ? Q.y : P.y) - py;
+            vz = (double)(pv ? Q.z : P.z) - pz;
+            lv = sqrt_dp(fma(vx, vx, fma(vy, vy, fma(vz, vz, LEN2_FLOOR))));
         } else {
-            vx = v0x; vy = v0y; vz = v0z; lv = l0; pv = p0;
+            vx = fx; vy = fy; vz = fz; lv = lf; pv = pf;
         }
-        const bool both = pu && pv;
-        const double w = both ? rcp_dp(lu + lv) : 0.0;
-        ax = fma(w, uy * vz - uz * vy, ax);
-        ay = fma(w, uz * vx - ux * vz, ay);
-        az = fma(w, ux * vy - uy * vx, az);
-        any |= both;
+        if (t == 0) {
+            fx = vx; fy = vy; fz = vz; lf = lv; pf = pv;
+        } else {
+            const double w = rcp_dp(lu + lv);
+            ax = fma(w, fma(uy, vz, -uz * vy), ax);
+            ay = fma(w, fma(uz, vx, -ux * vz), ay);
+            az = fma(w, fma(ux, vy, -uy * vx), az);
+            any |= pu && pv;
+        }
         ux = vx; uy = vy; uz = vz; lu = lv; pu = pv;
     }
     const double n2 = ax * ax + ay * ay + az * az;
@@ -368,39 +383,35 @@ __device__ __forceinline__ void vertex_normal(const float* sx, const float* sy, 
     }
 }
 
+__device__ __forceinline__ int vid_of(float4 c) { return __float_as_int(c.w); }
+
 // ---------------------------------------------------------------------------
 // The per-tile fused stage.  LDS columns lc = -1 .. TWe+1 of the tile (global
 // column k0 + lc, wrapped on a closed cylinder) hold the kept points'
-// coordinates (NaN = empty cell); LDS cell lx = (lc + 1) * H + i.  Own cells are
-// lc in [0, TWe); the right column lc = TWe belongs to the next tile but its
-// normals are needed for the joins that leave the tile.  Index l = lx - H runs
-// over own cells and then the right column.
+// coordinates (NaN = empty cell) and vertex ids; LDS cell lx = (lc + 1) * H + i.
+// Own cells are lc in [0, TWe); the right column lc = TWe belongs to the next
+// tile but its normals are needed for the joins that leave the tile.  Index
+// l = lx - H runs over own cells and then the right column.
 template <int NT, int MAXC>
 __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int XC = MAXC + 3 * MAX_RINGS;  // coordinate cells incl. halo
     constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
     constexpr int RX = (XC + NT - 1) / NT;
     constexpr int RN = (NC + NT - 1) / NT;
+    constexpr int RO = (MAXC + NT - 1) / NT;
     constexpr int NW = NT / 64;
-    // sx/sy/sz: coordinates, then (after the normal stage) normals indexed by l
-    __shared__ float sx[XC], sy[XC], sz[XC];
-    __shared__ int svid[NC];     // vertex index of l (frame-local), -1 = empty
-    __shared__ int saux[MAXC];   // kept point index, then triangle start, then union-find parent
+    // sc: (x, y, z, vertex id) by lx; after the normal stage (nx, ny, nz, vertex id) by l
+    __shared__ float4 sc[XC];
+    __shared__ int saux[MAXC];        // kept point index, then triangle start, then union-find parent
     __shared__ uint8_t sedge[MAXC];   // similar joins of own cells: bit 0 A (down), 1 C (right), 2 B (diagonal)
-    __shared__ int s_cnt[3][RN][NW];  // per round and wave: vertices, own vertices, triangles
-    __shared__ int s_misc[3];         // ticket, vertex base, triangle base
+    __shared__ int s_cnt[2][RN][NW];  // per round and wave: vertices, triangles
+    __shared__ int s_misc[4];         // vertex base, triangle base, own vertices, own triangles
 
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
-    const uint32_t epoch = hdr->epoch;
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    while (true) {
-        __syncthreads();  // LDS of the previous tile is free
-        if (threadIdx.x == 0) s_misc[0] = atomicAdd(ws.tickets, 1);
-        __syncthreads();
-        const int t = s_misc[0];
-        if (t >= hdr->total_tiles) break;
-        const FrameDesc* fd = F + frame_of_tile(F, nf, t);
+    for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
         const int H = fd->H, Wp = fd->Wp, wrap = fd->wrap;
         const float inv_h = 1.0f / (float)H;
         const int lt = t - fd->tile_off;
@@ -414,10 +425,10 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
         const float* __restrict__ nin = fd->normals_in;
         const int64_t np = fd->n_points;
         const double tx = fd->thr[0], ty = fd->thr[1], tz = fd->thr[2];
-        int* const forest = ws.forest + fd->cell_off;
+        const int cell_off = (int)fd->cell_off;
+        __syncthreads();  // LDS of the previous tile is free
 
-        // 1. keys of the tile and its halo columns, then the kept points (loads
-        //    issued back to back so their latencies overlap)
+        // 1. keys of the tile and its halo columns
         uint64_t key[RX];
 #pragma unroll
         for (int r = 0; r < RX; ++r) {
@@ -435,6 +446,24 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
                 if (in) key[r] = keys[(int64_t)k * H + i];
             }
         }
+        // 2. vertex and triangle bases: the counts of the frame's earlier tiles
+        if (wv == 0) {
+            int sv = 0, st = 0;
+#pragma unroll 4
+            for (int j = fd->tile_off + lane; j < t; j += 64) {
+                sv += ws.tile_v[j];
+                st += ws.tile_t[j];
+            }
+            sv = wave_sum(sv);
+            st = wave_sum(st);
+            if (lane == 0) {
+                s_misc[0] = sv;
+                s_misc[1] = st;
+                s_misc[2] = ws.tile_v[t];
+                s_misc[3] = ws.tile_t[t];
+            }
+        }
+        // 3. the kept points
         float cx[RX], cy[RX], cz[RX];
 #pragma unroll
         for (int r = 0; r < RX; ++r) {
@@ -450,15 +479,13 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
         for (int r = 0; r < RX; ++r) {
             const int lx = threadIdx.x + r * NT;
             if (lx < nx) {
-                sx[lx] = cx[r];
-                sy[lx] = cy[r];
-                sz[lx] = cz[r];
+                sc[lx] = make_float4(cx[r], cy[r], cz[r], __int_as_float(-1));
                 if (lx >= H && lx < H + nown) saux[lx - H] = (int)(uint32_t)key[r];
             }
         }
         __syncthreads();
 
-        // 2. local numbering in firing order: own cells, then the right column.
+        // 4. numbering in firing order: own cells, then the right column.
         //    Wave prefixes from ballots; per-wave totals go through LDS.
         bool vv[RN];
         int lv[RN], ltr[RN];
@@ -469,17 +496,16 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
             int ntri = 0;
             if (l < nscan) {
                 const int lx = l + H;
-                v = sx[lx] == sx[lx];
+                v = sc[lx].x == sc[lx].x;
                 const int i = l - div_small(l, inv_h) * H;
                 if (v && l < nown && i + 1 < H) {
-                    const bool a = sx[lx + 1] == sx[lx + 1];
-                    const bool b = sx[lx + H + 1] == sx[lx + H + 1];
-                    const bool c = sx[lx + H] == sx[lx + H];
+                    const bool a = sc[lx + 1].x == sc[lx + 1].x;
+                    const bool b = sc[lx + H + 1].x == sc[lx + H + 1].x;
+                    const bool c = sc[lx + H].x == sc[lx + H].x;
                     ntri = (int)(a && b) + (int)(b && c);
                 }
             }
             const uint64_t bv = __ballot(v);
-            const uint64_t bo = __ballot(v && l < nown);
             const uint64_t b1 = __ballot(ntri & 1);
             const uint64_t b2 = __ballot(ntri >> 1);
             vv[r] = v;
@@ -487,98 +513,75 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
             ltr[r] = lanes_below(b1) + 2 * lanes_below(b2);
             if (lane == 0) {
                 s_cnt[0][r][wv] = __popcll(bv);
-                s_cnt[1][r][wv] = __popcll(bo);
-                s_cnt[2][r][wv] = __popcll(b1) + 2 * __popcll(b2);
+                s_cnt[1][r][wv] = __popcll(b1) + 2 * __popcll(b2);
             }
         }
         __syncthreads();
-        int own_v = 0, own_t = 0, run_v = 0, run_t = 0;
+        {
+            int run_v = 0, run_t = 0;
 #pragma unroll
-        for (int r = 0; r < RN; ++r) {
+            for (int r = 0; r < RN; ++r) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const int cv = s_cnt[0][r][w], ct = s_cnt[2][r][w];
-                own_v += s_cnt[1][r][w];
-                own_t += ct;
-                if (w == wv) { lv[r] += run_v; ltr[r] += run_t; }
-                run_v += cv;
-                run_t += ct;
+                for (int w = 0; w < NW; ++w) {
+                    if (w == wv) { lv[r] += run_v; ltr[r] += run_t; }
+                    run_v += s_cnt[0][r][w];
+                    run_t += s_cnt[1][r][w];
+                }
             }
         }
+        const int vbase = s_misc[0], tbase = s_misc[1], own_v = s_misc[2];
+        const bool last_tile = lt + 1 == fd->n_tiles;
+        if (threadIdx.x == 0 && last_tile) {
+            fd->counts[0] = vbase + own_v;
+            fd->counts[1] = tbase + s_misc[3];
+        }
+        const int vbase_next = last_tile ? 0 : vbase + own_v;  // seam: the right column is column 0
 
-        // 3. frame-wide bases: publish this tile's counts and look back at its
-        //    predecessors; vertices on wave 0, triangles on wave 1
-        if (wv < 2) {
-            uint64_t* st = (wv == 0) ? ws.stat_v : ws.stat_t;
-            const int own = (wv == 0) ? own_v : own_t;
-            if (lane == 0) st_store(st + t, st_pack(epoch, lt == 0 ? 2u : 1u, (uint32_t)own));
-            const int pre = (lt > 0) ? lookback(st, t, fd->tile_off, epoch) : 0;
-            if (lane == 0) {
-                const bool bad = pre < 0 || pre >= (int)POISON;
-                if (lt > 0) st_store(st + t, st_pack(epoch, 2u, bad ? POISON : (uint32_t)(pre + own)));
-                s_misc[1 + wv] = bad ? -1 : pre;
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const bool bad = s_misc[1] < 0 || s_misc[2] < 0;
-            ws.tile_v[t] = own_v;
-            ws.tile_vbase[t] = bad ? -1 : s_misc[1];
-            if (bad) {
-                s_misc[1] = -1;
-                fd->counts[0] = -1;
-                fd->counts[1] = -1;
-                fd->counts[2] = -1;
-            } else if (lt + 1 == fd->n_tiles) {
-                fd->counts[0] = s_misc[1] + own_v;
-                fd->counts[1] = s_misc[2] + own_t;
-            }
-        }
-        __syncthreads();
-        const int vbase = s_misc[1], tbase = s_misc[2];
-        if (vbase < 0) continue;  // the frame reports counts of -1
-        const int vbase_next = (lt + 1 == fd->n_tiles) ? 0 : vbase + own_v;  // seam: column 0
-
-        // 4. vertex ids; vertices, their points and triangle starts
+        // 5. vertex ids; vertices, their points and triangle starts
+        int vid[RN];
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
             const int l = threadIdx.x + r * NT;
-            if (l < nscan) {
-                int vid = -1;
-                if (vv[r]) vid = (l < nown) ? vbase + lv[r] : vbase_next + (lv[r] - own_v);
-                svid[l] = vid;
-                if (l < nown && vv[r]) {
-                    const int lx = l + H;
-                    float* vo = fd->vertices + 3 * (int64_t)vid;
-                    vo[0] = sx[lx];
-                    vo[1] = sy[lx];
-                    vo[2] = sz[lx];
-                    if (fd->vpoint) fd->vpoint[vid] = saux[l];
+            vid[r] = -1;
+            if (l < nscan && vv[r]) {
+                const int lx = l + H;
+                vid[r] = (l < nown) ? vbase + lv[r] : vbase_next + (lv[r] - own_v);
+                sc[lx].w = __int_as_float(vid[r]);
+                if (l < nown) {
+                    const float4 p = sc[lx];
+                    float* vo = fd->vertices + 3 * (int64_t)vid[r];
+                    vo[0] = p.x;
+                    vo[1] = p.y;
+                    vo[2] = p.z;
+                    if (fd->vpoint) fd->vpoint[vid[r]] = saux[l];
                     saux[l] = tbase + ltr[r];
                 }
             }
         }
         __syncthreads();
 
-        // 5. triangles T_a = (p, A, B), T_b = (p, B, C) of each own anchor
-        for (int l = threadIdx.x; l < nown; l += NT) {
-            const int p = svid[l];
+        // 6. triangles T_a = (p, A, B), T_b = (p, B, C) of each own anchor
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l >= nown || !vv[r]) continue;
             const int i = l - div_small(l, inv_h) * H;
-            if (p < 0 || i + 1 >= H) continue;
-            const int a = svid[l + 1], b = svid[l + H + 1], c = svid[l + H];
+            if (i + 1 >= H) continue;
+            const int lx = l + H;
+            const int a = vid_of(sc[lx + 1]), b = vid_of(sc[lx + H + 1]), c = vid_of(sc[lx + H]);
             int ti = saux[l];
             if (a >= 0 && b >= 0) {
                 int32_t* to = fd->tris + 3 * (int64_t)ti;
-                to[0] = p; to[1] = a; to[2] = b;
+                to[0] = vid[r]; to[1] = a; to[2] = b;
                 ++ti;
             }
             if (b >= 0 && c >= 0) {
                 int32_t* to = fd->tris + 3 * (int64_t)ti;
-                to[0] = p; to[1] = b; to[2] = c;
+                to[0] = vid[r]; to[1] = b; to[2] = c;
             }
         }
 
-        // 6. normals of own cells and the right column (or the given ones), kept
+        // 7. normals of own cells and the right column (or the given ones), kept
         //    in registers until every thread is done reading coordinates
         float nrm[RN][3];
 #pragma unroll
@@ -586,17 +589,16 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
             const int l = threadIdx.x + r * NT;
             nrm[r][0] = nrm[r][1] = nrm[r][2] = 0.0f;
             if (l < nscan && vv[r]) {
-                const int vid = svid[l];
                 if (nin) {
-                    nrm[r][0] = nin[3 * (int64_t)vid];
-                    nrm[r][1] = nin[3 * (int64_t)vid + 1];
-                    nrm[r][2] = nin[3 * (int64_t)vid + 2];
+                    nrm[r][0] = nin[3 * (int64_t)vid[r]];
+                    nrm[r][1] = nin[3 * (int64_t)vid[r] + 1];
+                    nrm[r][2] = nin[3 * (int64_t)vid[r] + 2];
                 } else {
                     const int i = l - div_small(l, inv_h) * H;
-                    vertex_normal(sx, sy, sz, l + H, i, H, nrm[r][0], nrm[r][1], nrm[r][2]);
+                    vertex_normal(sc, l + H, i, H, nrm[r][0], nrm[r][1], nrm[r][2]);
                 }
                 if (l < nown) {
-                    float* no = fd->normals + 3 * (int64_t)vid;
+                    float* no = fd->normals + 3 * (int64_t)vid[r];
                     no[0] = nrm[r][0];
                     no[1] = nrm[r][1];
                     no[2] = nrm[r][2];
@@ -607,45 +609,69 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
             const int l = threadIdx.x + r * NT;
-            if (l < nscan) {
-                sx[l] = nrm[r][0];
-                sy[l] = nrm[r][1];
-                sz[l] = nrm[r][2];
-            }
+            if (l < nscan) sc[l] = make_float4(nrm[r][0], nrm[r][1], nrm[r][2], __int_as_float(vid[r]));
         }
         __syncthreads();
 
-        // 7. segments inside the tile.  Similar joins of own cells first (A down,
-        //    C right, B diagonal; C and B into the right column leave the tile).
-        for (int l = threadIdx.x; l < nown; l += NT) {
+        // 8. similar joins of own cells (A down, C right, B diagonal; C and B into
+        //    the right column leave the tile)
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l >= nown) continue;
             const int i = l - div_small(l, inv_h) * H;
-            const float ax = sx[l], ay = sy[l], az = sz[l];
+            const float4 a = sc[l];
             int e = 0;
-            if (i + 1 < H && similar(ax, ay, az, sx[l + 1], sy[l + 1], sz[l + 1], tx, ty, tz)) e |= 1;
-            if (similar(ax, ay, az, sx[l + H], sy[l + H], sz[l + H], tx, ty, tz)) e |= 2;
-            if (i + 1 < H && similar(ax, ay, az, sx[l + H + 1], sy[l + H + 1], sz[l + H + 1], tx, ty, tz)) e |= 4;
+            if (i + 1 < H && similar(a, sc[l + 1], tx, ty, tz)) e |= 1;
+            if (similar(a, sc[l + H], tx, ty, tz)) e |= 2;
+            if (i + 1 < H && similar(a, sc[l + H + 1], tx, ty, tz)) e |= 4;
             sedge[l] = (uint8_t)e;
         }
         __syncthreads();
-        //    Vertical runs: each cell points at the cell above when joined to it,
-        //    then pointer jumping makes every cell point at its run's top cell.
+
+        // 9. vertical runs: every own cell's parent is the top cell of its run of
+        //    A joins, found with a ballot of run starts over each 64-cell chunk;
+        //    a run that enters the chunk from above takes the previous chunk's head
         int* const sparent = saux;
-        for (int l = threadIdx.x; l < nown; l += NT) {
-            const int i = l - div_small(l, inv_h) * H;
-            sparent[l] = (i >= 1 && (sedge[l - 1] & 1)) ? l - 1 : l;
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            bool start = true;
+            if (l < nown) {
+                const int i = l - div_small(l, inv_h) * H;
+                start = !(i >= 1 && (sedge[l - 1] & 1));
+            }
+            const uint64_t S = __ballot(start);
+            const uint64_t mine = S & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull));
+            const int head = mine ? (l - lane) + 63 - __builtin_clzll(mine) : -1;
+            if (l < nown) sparent[l] = head;
         }
         __syncthreads();
-        for (int span = 1; span < H; span <<= 1) {
-            for (int l = threadIdx.x; l < nown; l += NT) sparent[l] = sparent[sparent[l]];
-            __syncthreads();
+        if (64 % H != 0) {
+            // a run of at most 128 cells spans at most three chunks: two passes
+            for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                for (int r = 0; r < RO; ++r) {
+                    const int l = threadIdx.x + r * NT;
+                    if (l < nown && sparent[l] < 0) {
+                        const int h = sparent[(l & ~63) - 1];
+                        if (h >= 0) sparent[l] = h;
+                    }
+                }
+                __syncthreads();
+            }
         }
-        //    Unions across columns.  A right (C) join is implied when the cell above
-        //    has one and both cells continue their runs downwards; a diagonal (B)
-        //    join is implied by A then C, or C then A.
-        for (int l = threadIdx.x; l < nown; l += NT) {
-            const int i = l - div_small(l, inv_h) * H;
+
+        // 10. unions across columns.  A right (C) join is implied when the cell
+        //     above has one and both cells continue their runs downwards; a
+        //     diagonal (B) join is implied by A then C, or C then A.
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l >= nown) continue;
             const int lc = div_small(l, inv_h);
             if (lc + 1 >= TWe) continue;
+            const int i = l - lc * H;
             const int e = sedge[l];
             if (e & 2) {
                 const bool implied = i >= 1 && (sedge[l - 1] & 3) == 3 && (sedge[l - 1 + H] & 1);
@@ -656,30 +682,49 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
                 if (!implied) lds_union(sparent, l, l + H + 1);
             }
         }
-        // joins leaving through the right edge: (last column, C) and (last column, B)
-        int2* border = ws.border + fd->border_off + (int64_t)lt * 2 * H;
-        for (int i = threadIdx.x; i < H; i += NT) {
-            const int l = (TWe - 1) * H + i;
-            const int e = sedge[l];
-            border[2 * i] = (e & 2) ? make_int2(svid[l], svid[l + H]) : make_int2(-1, -1);
-            border[2 * i + 1] = (e & 4) ? make_int2(svid[l], svid[l + H + 1]) : make_int2(-1, -1);
-        }
         __syncthreads();
-        // local roots: the smallest cell of each local tree (no writes while reading)
-        for (int l = threadIdx.x; l < nown; l += NT) {
-            const int vid = svid[l];
-            if (vid < 0) continue;
-            int r = l;
-            for (int it = 0; it < nown && sparent[r] != r; ++it) r = sparent[r];
-            forest[vid] = svid[r];
+
+        // 11. joins leaving through the right edge, with the same implication
+        //     rules (A joins of the right column from its normals), into the
+        //     tile's border slots: 2i for the C join of ring i, 2i+1 for its B join
+        {
+            int2* const slots = ws.border + fd->border_off + (int64_t)lt * 2 * H;
+            for (int i = threadIdx.x; i < H; i += NT) {
+                const int l = (TWe - 1) * H + i;
+                const int e = sedge[l];
+                const int a = cell_off + vid_of(sc[l]);
+                int2 jc = make_int2(-1, -1), jb = make_int2(-1, -1);
+                if ((e & 2) && !(i >= 1 && (sedge[l - 1] & 3) == 3 && similar(sc[l - 1 + H], sc[l + H], tx, ty, tz)))
+                    jc = make_int2(a, cell_off + vid_of(sc[l + H]));
+                if ((e & 4) && !(((e & 1) && (sedge[l + 1] & 2)) ||
+                                 ((e & 2) && similar(sc[l + H], sc[l + H + 1], tx, ty, tz))))
+                    jb = make_int2(a, cell_off + vid_of(sc[l + H + 1]));
+                slots[2 * i] = jc;
+                slots[2 * i + 1] = jb;
+            }
+        }
+
+        // 12. local roots: the smallest cell of each local tree (no writes while reading)
+        int* const forest = ws.forest;
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l >= nown || vid[r] < 0) continue;
+            int x = l;
+            for (int it = 0; it < nown && sparent[x] != x; ++it) x = sparent[x];
+            forest[cell_off + vid[r]] = cell_off + vid_of(sc[x]);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Global union-find on a frame's label array (vertex-indexed parents).
+// Global union-find on the batch's forest (batch-wide positions).
 __device__ __forceinline__ int g_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void g_store(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int g_find(int* P, int x) {
@@ -687,7 +732,7 @@ __device__ __forceinline__ int g_find(int* P, int x) {
         const int p = g_load(P + x);
         if (p == x) return x;
         const int gp = g_load(P + p);
-        if (gp != p) __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gp != p) g_store(P + x, gp);
         x = gp;
     }
     return x;
@@ -705,174 +750,158 @@ __device__ __forceinline__ void g_union(int* P, int a, int b) {
     }
 }
 
-// Largest frame f with F[f].border_off <= e.
-__device__ __forceinline__ int frame_of_border(const FrameDesc* F, int nf, int64_t e) {
-    int lo = 0, hi = nf - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (F[mid].border_off <= e) lo = mid; else hi = mid - 1;
+// Pointer jumping on one node: its parent becomes its grandparent until it
+// points at a root.  Run by many threads on the nodes of one chain at once, the
+// distance each node covers doubles per step.
+__device__ __forceinline__ void g_jump(int* P, int x) {
+    for (int it = 0; it < WALK_LIMIT; ++it) {
+        const int p = g_load(P + x);
+        const int gp = g_load(P + p);
+        if (gp == p) return;
+        g_store(P + x, gp);
     }
-    return lo;
 }
 
-// One thread per border slot of the batch (the similar joins leaving each tile
-// through its right edge).  Both ends are replaced by their current parents (any
-// ancestor works for a union), and a join whose (frame, parent pair) repeats one
-// of the four slots before it -- usually the rows above, joining the same two
-// segments -- is skipped, which keeps most threads off the same two roots.
+// One thread per border slot written by k_tile.  Concurrent unions of
+// neighbouring tiles' segments link each tile's root to its left neighbour's, a
+// chain as long as the frame; after its union each thread therefore jumps the
+// two local roots it joined towards their root.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_merge(const BatchHeader* __restrict__ hdr, Workspace ws) {
-    __shared__ int3 s_pair[NT];
-    const FrameDesc* F = frames_of(hdr);
-    const int nf = hdr->n_frames;
-    const FrameDesc* last = F + nf - 1;
-    const int64_t total = last->border_off + (int64_t)last->n_tiles * 2 * last->H;
-    for (int64_t base = (int64_t)blockIdx.x * NT; base < total; base += (int64_t)gridDim.x * NT) {
-        const int64_t e = base + threadIdx.x;
-        int3 rr = make_int3(-1, -1, -1);
-        int* L = nullptr;
-        if (e < total) {
-            const int f = frame_of_border(F, nf, e);
-            const FrameDesc* fd = F + f;
-            const int2 ab = ws.border[e];
-            if (ab.x >= 0 && fd->counts[0] >= 0) {  // counts < 0: the frame failed in k_tile
-                L = ws.forest + fd->cell_off;
-                rr = make_int3(g_load(L + ab.x), g_load(L + ab.y), f);
-            }
-        }
-        __syncthreads();
-        s_pair[threadIdx.x] = rr;
-        __syncthreads();
-        if (rr.x >= 0) {
-            bool dup = false;
-#pragma unroll
-            for (int d = 1; d <= 4; ++d) {
-                if ((int)threadIdx.x >= d) {
-                    const int3 q = s_pair[threadIdx.x - d];
-                    dup |= (q.x == rr.x && q.y == rr.y && q.z == rr.z);
-                }
-            }
-            if (!dup) g_union(L, rr.x, rr.y);
-        }
+    const int n = hdr->total_border;
+    int* const P = ws.forest;
+    for (int e = blockIdx.x * NT + threadIdx.x; e < n; e += gridDim.x * NT) {
+        const int2 ab = ws.border[e];
+        if (ab.x < 0) continue;
+        const int ra = g_load(P + ab.x), rb = g_load(P + ab.y);
+        g_union(P, ra, rb);
+        g_jump(P, ra);
+        g_jump(P, rb);
     }
 }
 
-// Labels.  Per tile, in ticket order: the tile's segment roots (forest entry
-// equal to itself) are ranked in firing order across the frame (look-back over
-// tiles) and their forest entries become -(1 + rank).  Every other vertex walks
-// its forest path until it meets a negative entry, which carries its segment's
-// label.  A root is the smallest vertex of its segment, so every path stays in
-// this tile or earlier ones; a root of an earlier tile that is not ranked yet is
-// waited for (its tile holds an earlier ticket and never waits on later tiles).
-// The tile's key cells are reset for the next call.
+// Roots.  Item b of a frame covers vertex slots [1024 b, 1024 b + 1024).  Every
+// vertex finds its segment root (walks halve the paths they take) and leaves
+// it, frame-local, in its label slot for k_resolve; the roots of each 64-slot
+// word are flagged in rootbits, each word gets the item's roots before it, and
+// the item its root count.  The item's key cells are reset for the next call.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_label(const BatchHeader* __restrict__ hdr, Workspace ws) {
-    constexpr int RV = 2048 / NT;   // vertex rounds: a tile owns at most 2048 vertices
+__global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int RV = VITEM / NT;
     constexpr int NW = NT / 64;
-    __shared__ int s_cnt[RV][NW];
-    __shared__ int s_misc[2];
+    static_assert(RV * NW == VITEM_WORDS, "one word per wave and round");
+    __shared__ int s_w[VITEM_WORDS];
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
-    const uint32_t epoch = hdr->epoch;
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    while (true) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_misc[0] = atomicAdd(ws.tickets + 1, 1);
-        __syncthreads();
-        const int t = s_misc[0];
-        if (t >= hdr->total_tiles) break;
-        const FrameDesc* fd = F + frame_of_tile(F, nf, t);
-        const int lt = t - fd->tile_off;
-        const bool frame_ok = fd->counts[0] >= 0;
-        int* const P = ws.forest + fd->cell_off;
-        int* const L = fd->labels;
-        const int vb = ws.tile_vbase[t], nv = ws.tile_v[t];
-
-        // 1. roots of the tile, ranked
-        uint32_t mine = 0, roots = 0;
-        int pre[RV], cur[RV];
+    int* const P = ws.forest;
+    for (int b = blockIdx.x; b < hdr->total_vitems; b += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::vitem_off>(F, nf, b);
+        const int lb = b - fd->vitem_off;
+        const int V = (int)max<int64_t>(fd->counts[0], 0);
+        const int base = (int)fd->cell_off;
+        const int v0 = lb * VITEM;
+        const int64_t wbase = (int64_t)b * VITEM_WORDS;   // == vitem_off * 16 + lb * 16
+        __syncthreads();  // s_w of the previous item has been read
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
-            const int k = threadIdx.x + r * NT;
-            const int v = vb + k;
-            cur[r] = v;
+            const int v = v0 + r * NT + threadIdx.x;
             bool isroot = false;
-            if (frame_ok && k < nv) {
-                mine |= 1u << r;
-                cur[r] = P[v];
-                isroot = cur[r] == v;
+            if (v < V) {
+                const int g = base + v;
+                const int p = g_load(P + g);
+                const int root = (p == g) ? g : g_find(P, p);
+                fd->labels[v] = root - base;
+                isroot = root == g;
             }
-            const uint64_t b = __ballot(isroot);
-            pre[r] = lanes_below(b);
-            if (lane == 0) s_cnt[r][wv] = __popcll(b);
-            roots |= (uint32_t)isroot << r;
+            const uint64_t bits = __ballot(isroot);
+            if (lane == 0) {
+                ws.rootbits[wbase + r * NW + wv] = bits;
+                s_w[r * NW + wv] = __popcll(bits);
+            }
         }
         __syncthreads();
-        int own_r = 0, run = 0;
+        if (wv == 0) {
+            const int c = lane < VITEM_WORDS ? s_w[lane] : 0;
+            int inc = c;
 #pragma unroll
-        for (int r = 0; r < RV; ++r) {
+            for (int d = 1; d < VITEM_WORDS; d <<= 1) {
+                const int y = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += y;
+            }
+            if (lane < VITEM_WORDS) ws.wprefix[wbase + lane] = (uint32_t)(inc - c);
+            if (lane == VITEM_WORDS - 1) ws.vitem_roots[b] = inc;
+        }
+        const int c1 = min(v0 + VITEM, fd->H * fd->Wp);
+        uint64_t* keys = ws.keys + fd->cell_off;
+        for (int c = v0 + threadIdx.x; c < c1; c += NT) keys[c] = KEY_EMPTY;
+    }
+}
+
+// Rank bases, one frame per workgroup: each labelling item's root count is
+// replaced by the roots of the frame before the item (an exclusive scan in
+// firing order), and the frame's label count K is written.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_scan(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int NW = NT / 64;
+    __shared__ int s_tot[NW];
+    const FrameDesc* F = frames_of(hdr);
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    for (int f = blockIdx.x; f < hdr->n_frames; f += gridDim.x) {
+        const FrameDesc* fd = F + f;
+        int32_t* const cnt = ws.vitem_roots + fd->vitem_off;
+        const int n = fd->n_vitem;
+        int run = 0;
+        for (int c0 = 0; c0 < n; c0 += NT) {
+            const int j = c0 + (int)threadIdx.x;
+            const int mine = j < n ? cnt[j] : 0;
+            int inc = mine;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += y;
+            }
+            __syncthreads();  // s_tot of the previous chunk has been read
+            if (lane == 63) s_tot[wv] = inc;
+            __syncthreads();
+            int before = 0, total = 0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                const int c = s_cnt[r][w];
-                own_r += c;
-                if (w == wv) pre[r] += run;
-                run += c;
+                if (w < wv) before += s_tot[w];
+                total += s_tot[w];
             }
+            if (j < n) cnt[j] = run + before + inc - mine;
+            run += total;
         }
-        if (wv == 0) {
-            if (lane == 0) st_store(ws.stat_r + t, st_pack(epoch, lt == 0 ? 2u : 1u, (uint32_t)own_r));
-            const int pr = (lt > 0) ? lookback(ws.stat_r, t, fd->tile_off, epoch) : 0;
-            const bool bad = pr < 0 || pr >= (int)POISON;
-            if (lane == 0) {
-                if (lt > 0) st_store(ws.stat_r + t, st_pack(epoch, 2u, bad ? POISON : (uint32_t)(pr + own_r)));
-                if (bad) fd->counts[2] = -1;
-                else if (lt + 1 == fd->n_tiles && frame_ok) fd->counts[2] = pr + own_r;
-                s_misc[1] = bad ? -1 : pr;
-            }
-        }
-        __syncthreads();
-        const int rbase = s_misc[1];
-        const bool ok = rbase >= 0 && frame_ok;
-        if (ok) {
-#pragma unroll
-            for (int r = 0; r < RV; ++r) {
-                if ((roots >> r) & 1u) {
-                    const int v = vb + threadIdx.x + r * NT;
-                    const int label = 1 + rbase + pre[r];
-                    __hip_atomic_store(P + v, -label, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    L[v] = label;
-                }
-            }
-        }
-        __syncthreads();
+        if (threadIdx.x == 0) fd->counts[2] = run;
+    }
+}
 
-        // 2. every other vertex: walk to a ranked root, all walks advancing together
-        uint32_t walking = ok ? (mine & ~roots) : 0u;
-        int spins = 0;
-        while (walking) {
+// label = 1 + (roots of the frame before the vertex's root, which k_flatten
+// left in the vertex's label slot): the roots of the frame before the root's
+// item, of the item before its word, and of the word before it.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int RV = VITEM / NT;
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    for (int b = blockIdx.x; b < hdr->total_vitems; b += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::vitem_off>(F, nf, b);
+        const int lb = b - fd->vitem_off;
+        const int V = (int)max<int64_t>(fd->counts[0], 0);
+        const int v0 = lb * VITEM;
+        const int64_t wframe = (int64_t)fd->vitem_off * VITEM_WORDS;
+        const int32_t* const ibase = ws.vitem_roots + fd->vitem_off;
 #pragma unroll
-            for (int r = 0; r < RV; ++r) {
-                if ((walking >> r) & 1u) {
-                    const int y = g_load(P + cur[r]);
-                    if (y < 0) {
-                        L[vb + threadIdx.x + r * NT] = -y;
-                        walking &= ~(1u << r);
-                    } else if (y != cur[r]) {
-                        cur[r] = y;
-                    }
-                }
-            }
-            if (walking && ++spins > SPIN_LIMIT) {
-                fd->counts[2] = -1;
-                break;
+        for (int r = 0; r < RV; ++r) {
+            const int v = v0 + r * NT + threadIdx.x;
+            if (v < V) {
+                const int root = fd->labels[v];
+                const int64_t w = wframe + (root >> 6);
+                const uint64_t below = ws.rootbits[w] & ((1ull << (root & 63)) - 1ull);
+                fd->labels[v] = 1 + ibase[root / VITEM] + (int)ws.wprefix[w] + __popcll(below);
             }
         }
-
-        const int H = fd->H;
-        const int k0 = lt * fd->TW;
-        const int TWe = min(fd->TW, fd->Wp - k0);
-        uint64_t* keys = ws.keys + fd->cell_off + (int64_t)k0 * H;
-        for (int l = threadIdx.x; l < H * TWe; l += NT) keys[l] = KEY_EMPTY;
     }
 }
 
@@ -882,7 +911,11 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
                         hipStream_t stream, hipEvent_t* ev) {
     constexpr int NT = 256;
     const int g_tiles = max(1, min(cfg.grid, cfg.max_tiles));
+    const int g_count = max(1, min(2 * cfg.grid, cfg.max_tiles));
     const int g_pblk = max(1, min(cfg.grid, cfg.max_pblk));
+    const int g_vitem = max(1, min(2 * cfg.grid, cfg.max_vitems));
+    const int g_border = max(1, min(2 * cfg.grid, (cfg.max_border + NT - 1) / NT));
+    const int g_frames = max(1, min(cfg.grid, cfg.max_frames));
     int n = 0;
     hipError_t e = hipSuccess;
     auto mark = [&]() {
@@ -893,14 +926,24 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
     k_bin<NT><<<g_pblk, NT, 0, stream>>>(d_hdr, ws);
     mark();
     switch (cfg.tile_cells) {
+        case 512: k_count<NT, 512><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
+        case 2048: k_count<NT, 2048><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
+        default: k_count<NT, 1024><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
+    }
+    mark();
+    switch (cfg.tile_cells) {
         case 512: k_tile<NT, 512><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
         case 2048: k_tile<NT, 2048><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
         default: k_tile<NT, 1024><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
     }
     mark();
-    k_merge<NT><<<g_tiles, NT, 0, stream>>>(d_hdr, ws);
+    k_merge<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);
     mark();
-    k_label<NT><<<g_tiles, NT, 0, stream>>>(d_hdr, ws);
+    k_flatten<NT><<<g_vitem, NT, 0, stream>>>(d_hdr, ws);
+    mark();
+    k_scan<NT><<<g_frames, NT, 0, stream>>>(d_hdr, ws);
+    mark();
+    k_resolve<NT><<<g_vitem, NT, 0, stream>>>(d_hdr, ws);
     mark();
     const hipError_t le = hipGetLastError();
     return le != hipSuccess ? le : e;
