@@ -44,9 +44,9 @@ def stage_bytes(stage, N, V, T):
     not the key grid or other scratch).  N input points, V vertices, T triangles."""
     if stage == "bin":
         return 12 * N                         # xyz of every input point
-    if stage == "tile":
-        return 12 * V + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T  # kept xyz in; vertices,
-        # normals, vertex_point, local labels, triangles out
+    if stage == "geom":
+        return 12 * V + 12 * V + 12 * V + 4 * V + 12 * T  # kept xyz in; vertices, normals,
+        # vertex_point, triangles out
     if stage == "label":
         return 8 * V                          # segment root read + label written
     return 0

@@ -33,6 +33,7 @@ struct lidar_ctx {
     int32_t* forest = nullptr;    // same capacity as keys
     int64_t keys_cap = 0;
     int32_t* tile_buf = nullptr;  // 2 int32 arrays of tiles_cap: vertices, triangles per tile
+    uint64_t* occ = nullptr;      // OCC_WORDS per tile
     int64_t tiles_cap = 0;
     uint64_t* rootbits = nullptr; // VITEM_WORDS per labelling item
     uint32_t* wprefix = nullptr;  // VITEM_WORDS per labelling item
@@ -96,6 +97,7 @@ struct lidar_ctx {
         ws.forest = forest;
         ws.tile_v = tile_buf;
         ws.tile_t = tile_buf + tiles_cap;
+        ws.occ = occ;
         ws.rootbits = rootbits;
         ws.wprefix = wprefix;
         ws.vitem_roots = vitem_roots;
@@ -207,6 +209,7 @@ void lidar_ctx_destroy(lidar_ctx* c) {
     if (c->keys) (void)hipFree(c->keys);
     if (c->forest) (void)hipFree(c->forest);
     if (c->tile_buf) (void)hipFree(c->tile_buf);
+    if (c->occ) (void)hipFree(c->occ);
     if (c->rootbits) (void)hipFree(c->rootbits);
     if (c->wprefix) (void)hipFree(c->wprefix);
     if (c->vitem_roots) (void)hipFree(c->vitem_roots);
@@ -368,9 +371,12 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         }
         if (tiles > c->tiles_cap) {
             if (c->tile_buf) (void)hipFree(c->tile_buf);
+            if (c->occ) (void)hipFree(c->occ);
             c->tile_buf = nullptr;
+            c->occ = nullptr;
             const int64_t cap = std::max<int64_t>(tiles, c->tiles_cap * 3 / 2);
-            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess) {
+            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess ||
+                hipMalloc(&c->occ, sizeof(uint64_t) * OCC_WORDS * cap) != hipSuccess) {
                 c->tiles_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate tile arrays");
             }

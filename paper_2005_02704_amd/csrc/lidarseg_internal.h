@@ -13,6 +13,8 @@ constexpr int VITEM = 1024;                  // vertex slots per labelling work 
 constexpr int VITEM_WORDS = VITEM / 64;      // 64-bit root-flag words per labelling item
 constexpr int64_t MAX_CELLS = 1ll << 29;     // per frame; keeps every count below 2^30
 constexpr int64_t MAX_BATCH_CELLS = (1ll << 31) - VITEM;  // forest positions are int32
+constexpr int MAX_TILE_CELLS = 2048;
+constexpr int OCC_WORDS = MAX_TILE_CELLS / 64;        // occupancy words per tile
 
 // One frame of a batch, as the kernels see it.  Lives in device memory right
 // after a BatchHeader; all offsets index the context's workspace arrays.
@@ -57,6 +59,8 @@ struct Workspace {
     int32_t* forest;      // union-find parent of each vertex, as a batch-wide position
     int32_t* tile_v;      // vertices owned by each tile
     int32_t* tile_t;      // triangles anchored in each tile
+    uint64_t* occ;        // per tile, OCC_WORDS words: occupancy of its own cells (bit l of
+                          // the tile's cell sequence, firing order from its first column)
     uint64_t* rootbits;   // per 64 vertex slots: which vertices are segment roots
     uint32_t* wprefix;    // per 64 vertex slots: roots of its labelling item before the word
     int32_t* vitem_roots; // per labelling item: its roots, then (after k_scan) the roots
@@ -82,7 +86,7 @@ struct LaunchCfg {
     int max_frames;
 };
 
-constexpr int N_STAGES = 7;  // bin, count, tile, merge, flatten, scan, label
+constexpr int N_STAGES = 9;  // bin, count, geom, cc, merge, compress, flatten, scan, label
 
 // Enqueues the chain; when stage_events is non-null (N_STAGES + 1 events) an
 // event is recorded before the first kernel and after each kernel.

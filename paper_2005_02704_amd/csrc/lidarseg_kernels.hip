@@ -1,6 +1,6 @@
 // HIP kernels for gfx950 (MI355X): bin -> sub-sample -> mesh -> normals -> labels.
 //
-// One batch of frames runs as a chain of seven grid-stride kernels; each kernel
+// One batch of frames runs as a chain of nine grid-stride kernels; each kernel
 // walks its work items (point blocks, lattice tiles, border slots, blocks of
 // vertex slots or frames) across every frame of the batch, reading the
 // per-frame descriptors from device memory, so the same launches (and the same
@@ -9,13 +9,15 @@
 //
 // Stage map (Mukherjee et al., PReMI 2019, Section 2):
 //   k_bin      points -> (ring, firing) cell, sub-sampling, nearest return     [opening paragraph]
-//   k_count    vertices and triangles owned by each tile                       [Mesh Construction]
-//   k_tile     per tile in LDS: vertex and triangle numbering, mesh triangles,
-//              normals, similarity of joins, local segments                   [Mesh Construction,
-//                                                                               Normal Estimation, Algorithm 1]
+//   k_count    vertices, triangles and occupancy bits of each tile             [Mesh Construction]
+//   k_geom     per tile in LDS: vertex and triangle numbering, mesh triangles,
+//              normals                                                         [Mesh Construction,
+//                                                                               Normal Estimation]
+//   k_cc       per tile in LDS: similarity of joins, local segments           [Algorithm 1]
 //   k_merge    unions of the similar joins that cross tile borders             [Algorithm 1]
+//   k_compress pointer jumping on the segments joined across borders
 //   k_flatten  every vertex to its segment root; roots flagged; key cells reset
-//   k_scan     per frame: roots before each 64-vertex word (their rank base)
+//   k_scan     per frame: roots before each labelling item (their rank base)
 //   k_resolve  label = 1 + rank of the vertex's root
 //
 // Algorithm 1 floods through neighbours whose normal components differ by less
@@ -198,7 +200,8 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
 
 // ---------------------------------------------------------------------------
 // Vertices and triangles owned by each tile (from the key grid alone), so that
-// k_tile can number its vertices and triangles without waiting on other tiles.
+// the tile stages can number their vertices and triangles without waiting on
+// other tiles, and the occupancy bits of the tile's cells.
 // A vertex is an occupied cell; own anchor (i, k) with i+1 < H has triangle
 // T_a = (p, A, B) and T_b = (p, B, C) when all three corners are occupied.
 template <int NT, int MAXC>
@@ -251,6 +254,14 @@ __global__ __launch_bounds__(NT) void k_count(const BatchHeader* __restrict__ hd
                 }
             }
         }
+        // occupancy words of the own cells (64-cell chunk r * NW + wv is one ballot)
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            const int chunk = r * NW + wv;
+            const uint64_t m = __ballot(l < nown && socc[l]);
+            if (lane == 0 && chunk < MAXC / 64) ws.occ[(int64_t)t * OCC_WORDS + chunk] = m;
+        }
         nv = wave_sum(nv);
         nt = wave_sum(nt);
         if (lane == 0) {
@@ -298,11 +309,11 @@ __device__ __forceinline__ void lds_union(int* P, int a, int b) {
 }
 
 // Algorithm 1's test: both vertices have normals and every component differs by
-// strictly less than its threshold.  Differences of two floats are exact in FP64.
+// strictly less than its threshold.  Differences of two floats are exact in
+// FP64.  A vertex without a normal carries NaN components here, which fail
+// every comparison.
 __device__ __forceinline__ bool similar(float4 a, float4 b, double tx, double ty, double tz) {
-    const bool ha = !(a.x == 0.0f && a.y == 0.0f && a.z == 0.0f);
-    const bool hb = !(b.x == 0.0f && b.y == 0.0f && b.z == 0.0f);
-    return ha && hb && fabs((double)a.x - (double)b.x) < tx && fabs((double)a.y - (double)b.y) < ty &&
+    return fabs((double)a.x - (double)b.x) < tx && fabs((double)a.y - (double)b.y) < ty &&
            fabs((double)a.z - (double)b.z) < tz;
 }
 
@@ -386,25 +397,52 @@ __device__ __forceinline__ void vertex_normal(const float4* sc, int lx, int i, i
 __device__ __forceinline__ int vid_of(float4 c) { return __float_as_int(c.w); }
 
 // ---------------------------------------------------------------------------
-// The per-tile fused stage.  LDS columns lc = -1 .. TWe+1 of the tile (global
+// Vertex ids of the l-sequence of a tile (own cells, then the right column)
+// from per-lane occupancy: wave prefixes from ballots, the (round, wave) totals
+// scanned by every wave itself after one barrier.  vid[r] holds the rank within
+// the round on entry (-1 = empty) and the frame's vertex id on exit.
+template <int NT, int RN>
+__device__ __forceinline__ void number_cells(int (&vid)[RN], const int* s_cnt, int vbase, int vbase_next,
+                                             int own_v, int nown, int lane, int wv) {
+    constexpr int NW = NT / 64;
+    const int c = lane < RN * NW ? (s_cnt[lane] & 0xffff) : 0;
+    int inc = c;
+#pragma unroll
+    for (int d = 1; d < RN * NW; d <<= 1) {
+        const int y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    const int exc = inc - c;
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+        const int pre = __shfl(exc, r * NW + wv, 64);
+        const int l = (int)threadIdx.x + NT * r;
+        if (vid[r] < 0) continue;
+        const int rank = pre + vid[r];
+        vid[r] = (l < nown) ? vbase + rank : vbase_next + (rank - own_v);
+    }
+}
+
+// Mesh stage, per tile in LDS.  Columns lc = -1 .. TWe+1 of the tile (global
 // column k0 + lc, wrapped on a closed cylinder) hold the kept points'
 // coordinates (NaN = empty cell) and vertex ids; LDS cell lx = (lc + 1) * H + i.
 // Own cells are lc in [0, TWe); the right column lc = TWe belongs to the next
-// tile but its normals are needed for the joins that leave the tile.  Index
-// l = lx - H runs over own cells and then the right column.
+// tile (its vertex ids are needed by the triangles that reach into it).  Index
+// l = lx - H runs over own cells and then the right column; thread x handles
+// l = x + r * NT in round r, so every 64-cell chunk is one wave's round.
+// Writes vertices, vertex_point, triangles and normals.
+// 5 waves per SIMD at up to 1024 cells per tile
 template <int NT, int MAXC>
-__global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr, Workspace ws) {
+__global__ __launch_bounds__(NT, (MAXC <= 1024 ? 5 : 1)) void k_geom(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int XC = MAXC + 3 * MAX_RINGS;  // coordinate cells incl. halo
     constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
     constexpr int RX = (XC + NT - 1) / NT;
-    constexpr int RN = (NC + NT - 1) / NT;
-    constexpr int RO = (MAXC + NT - 1) / NT;
     constexpr int NW = NT / 64;
-    // sc: (x, y, z, vertex id) by lx; after the normal stage (nx, ny, nz, vertex id) by l
-    __shared__ float4 sc[XC];
-    __shared__ int saux[MAXC];        // kept point index, then triangle start, then union-find parent
-    __shared__ uint8_t sedge[MAXC];   // similar joins of own cells: bit 0 A (down), 1 C (right), 2 B (diagonal)
-    __shared__ int s_cnt[2][RN][NW];  // per round and wave: vertices, triangles
+    constexpr int RN = (NC + NT - 1) / NT;
+    static_assert(RN * NW <= 64, "one lane per (round, wave) in the prefix scan");
+    __shared__ float4 sc[XC];         // (x, y, z, vertex id) by lx
+    __shared__ int saux[MAXC];        // kept point index, then triangle start
+    __shared__ int s_cnt[RN * NW];    // per round and wave: vertices | triangles << 16
     __shared__ int s_misc[4];         // vertex base, triangle base, own vertices, own triangles
 
     const FrameDesc* F = frames_of(hdr);
@@ -424,26 +462,31 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
         const float* __restrict__ xyz = fd->xyz;
         const float* __restrict__ nin = fd->normals_in;
         const int64_t np = fd->n_points;
-        const double tx = fd->thr[0], ty = fd->thr[1], tz = fd->thr[2];
-        const int cell_off = (int)fd->cell_off;
+        const int step_i = NT % H, step_c = NT / H;   // (column, ring) advance per round
+        const int i0 = (int)threadIdx.x - div_small(threadIdx.x, inv_h) * H;
         __syncthreads();  // LDS of the previous tile is free
 
-        // 1. keys of the tile and its halo columns
+        // 1. keys of the tile and its halo columns (lx = tid + r * NT)
         uint64_t key[RX];
+        {
+            int col = div_small(threadIdx.x, inv_h);
+            int i = i0;
 #pragma unroll
-        for (int r = 0; r < RX; ++r) {
-            const int lx = threadIdx.x + r * NT;
-            key[r] = KEY_EMPTY;
-            if (lx < nx) {
-                const int col = div_small(lx, inv_h);
-                const int i = lx - col * H;
-                int k = k0 + col - 1;
-                bool in = true;
-                if (k < 0 || k >= Wp) {
-                    if (wrap) k = (k < 0) ? k + Wp : k - Wp;
-                    else in = false;
+            for (int r = 0; r < RX; ++r) {
+                const int lx = threadIdx.x + r * NT;
+                key[r] = KEY_EMPTY;
+                if (lx < nx) {
+                    int k = k0 + col - 1;
+                    bool in = true;
+                    if (k < 0 || k >= Wp) {
+                        if (wrap) k = (k < 0) ? k + Wp : k - Wp;
+                        else in = false;
+                    }
+                    if (in) key[r] = keys[(int64_t)k * H + i];
                 }
-                if (in) key[r] = keys[(int64_t)k * H + i];
+                i += step_i;
+                col += step_c;
+                if (i >= H) { i -= H; ++col; }
             }
         }
         // 2. vertex and triangle bases: the counts of the frame's earlier tiles
@@ -464,195 +507,277 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
             }
         }
         // 3. the kept points
-        float cx[RX], cy[RX], cz[RX];
+        {
+            float cx[RX], cy[RX], cz[RX];
 #pragma unroll
-        for (int r = 0; r < RX; ++r) {
-            cx[r] = cy[r] = cz[r] = __builtin_nanf("");
-            if (occupied(key[r], np)) {
-                const float* q = xyz + 3 * (int64_t)(uint32_t)key[r];
-                cx[r] = q[0];
-                cy[r] = q[1];
-                cz[r] = q[2];
+            for (int r = 0; r < RX; ++r) {
+                cx[r] = cy[r] = cz[r] = __builtin_nanf("");
+                if (occupied(key[r], np)) {
+                    const float* q = xyz + 3 * (int64_t)(uint32_t)key[r];
+                    cx[r] = q[0];
+                    cy[r] = q[1];
+                    cz[r] = q[2];
+                }
             }
-        }
 #pragma unroll
-        for (int r = 0; r < RX; ++r) {
-            const int lx = threadIdx.x + r * NT;
-            if (lx < nx) {
-                sc[lx] = make_float4(cx[r], cy[r], cz[r], __int_as_float(-1));
-                if (lx >= H && lx < H + nown) saux[lx - H] = (int)(uint32_t)key[r];
+            for (int r = 0; r < RX; ++r) {
+                const int lx = threadIdx.x + r * NT;
+                if (lx < nx) {
+                    sc[lx] = make_float4(cx[r], cy[r], cz[r], __int_as_float(-1));
+                    if (lx >= H && lx < H + nown) saux[lx - H] = (int)(uint32_t)key[r];
+                }
             }
         }
         __syncthreads();
 
-        // 4. numbering in firing order: own cells, then the right column.
-        //    Wave prefixes from ballots; per-wave totals go through LDS.
-        bool vv[RN];
-        int lv[RN], ltr[RN];
+        // 4. numbering in firing order (own cells, then the right column)
+        int vid[RN], ltr[RN];
+        {
+            int i = i0;
 #pragma unroll
-        for (int r = 0; r < RN; ++r) {
-            const int l = threadIdx.x + r * NT;
-            bool v = false;
-            int ntri = 0;
-            if (l < nscan) {
-                const int lx = l + H;
-                v = sc[lx].x == sc[lx].x;
-                const int i = l - div_small(l, inv_h) * H;
-                if (v && l < nown && i + 1 < H) {
-                    const bool a = sc[lx + 1].x == sc[lx + 1].x;
-                    const bool b = sc[lx + H + 1].x == sc[lx + H + 1].x;
-                    const bool c = sc[lx + H].x == sc[lx + H].x;
-                    ntri = (int)(a && b) + (int)(b && c);
+            for (int r = 0; r < RN; ++r) {
+                const int l = threadIdx.x + NT * r;
+                bool v = false;
+                int ntri = 0;
+                if (l < nscan) {
+                    const int lx = l + H;
+                    v = sc[lx].x == sc[lx].x;
+                    if (v && l < nown && i + 1 < H) {
+                        const bool a = sc[lx + 1].x == sc[lx + 1].x;
+                        const bool b = sc[lx + H + 1].x == sc[lx + H + 1].x;
+                        const bool c = sc[lx + H].x == sc[lx + H].x;
+                        ntri = (int)(a && b) + (int)(b && c);
+                    }
                 }
-            }
-            const uint64_t bv = __ballot(v);
-            const uint64_t b1 = __ballot(ntri & 1);
-            const uint64_t b2 = __ballot(ntri >> 1);
-            vv[r] = v;
-            lv[r] = lanes_below(bv);
-            ltr[r] = lanes_below(b1) + 2 * lanes_below(b2);
-            if (lane == 0) {
-                s_cnt[0][r][wv] = __popcll(bv);
-                s_cnt[1][r][wv] = __popcll(b1) + 2 * __popcll(b2);
+                const uint64_t bv = __ballot(v);
+                const uint64_t b1 = __ballot(ntri & 1);
+                const uint64_t b2 = __ballot(ntri >> 1);
+                vid[r] = v ? lanes_below(bv) : -1;
+                ltr[r] = lanes_below(b1) + 2 * lanes_below(b2);
+                if (lane == 0) s_cnt[r * NW + wv] = __popcll(bv) | ((__popcll(b1) + 2 * __popcll(b2)) << 16);
+                i += step_i;
+                if (i >= H) i -= H;
             }
         }
         __syncthreads();
-        {
-            int run_v = 0, run_t = 0;
-#pragma unroll
-            for (int r = 0; r < RN; ++r) {
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    if (w == wv) { lv[r] += run_v; ltr[r] += run_t; }
-                    run_v += s_cnt[0][r][w];
-                    run_t += s_cnt[1][r][w];
-                }
-            }
-        }
         const int vbase = s_misc[0], tbase = s_misc[1], own_v = s_misc[2];
         const bool last_tile = lt + 1 == fd->n_tiles;
         if (threadIdx.x == 0 && last_tile) {
             fd->counts[0] = vbase + own_v;
             fd->counts[1] = tbase + s_misc[3];
         }
-        const int vbase_next = last_tile ? 0 : vbase + own_v;  // seam: the right column is column 0
+        {
+            // triangle starts: the same scan over the upper halves
+            const int c = lane < RN * NW ? (s_cnt[lane] >> 16) : 0;
+            int inc = c;
+#pragma unroll
+            for (int d = 1; d < RN * NW; d <<= 1) {
+                const int y = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += y;
+            }
+            const int exc = inc - c;
+#pragma unroll
+            for (int r = 0; r < RN; ++r) ltr[r] += tbase + __shfl(exc, r * NW + wv, 64);
+        }
+        number_cells<NT, RN>(vid, s_cnt, vbase, last_tile ? 0 : vbase + own_v, own_v, nown, lane, wv);
 
-        // 5. vertex ids; vertices, their points and triangle starts
+        // 5. vertices, their points and triangle starts
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int l = threadIdx.x + NT * r;
+            if (vid[r] < 0) continue;
+            const int lx = l + H;
+            sc[lx].w = __int_as_float(vid[r]);
+            if (l < nown) {
+                const float4 p = sc[lx];
+                float* vo = fd->vertices + 3 * (int64_t)vid[r];
+                vo[0] = p.x;
+                vo[1] = p.y;
+                vo[2] = p.z;
+                if (fd->vpoint) fd->vpoint[vid[r]] = saux[l];
+                saux[l] = ltr[r];
+            }
+        }
+        __syncthreads();
+
+        // 6. triangles T_a = (p, A, B), T_b = (p, B, C) of each own anchor, and
+        //    the normals of the own vertices (or the given ones, copied)
+        {
+            int i = i0;
+#pragma unroll
+            for (int r = 0; r < RN; ++r) {
+                const int l = threadIdx.x + NT * r;
+                const int ir = i;
+                i += step_i;
+                if (i >= H) i -= H;
+                if (l >= nown || vid[r] < 0) continue;
+                const int lx = l + H;
+                if (ir + 1 < H) {
+                    const int a = vid_of(sc[lx + 1]), b = vid_of(sc[lx + H + 1]), c = vid_of(sc[lx + H]);
+                    int ti = saux[l];
+                    if (a >= 0 && b >= 0) {
+                        int32_t* to = fd->tris + 3 * (int64_t)ti;
+                        to[0] = vid[r]; to[1] = a; to[2] = b;
+                        ++ti;
+                    }
+                    if (b >= 0 && c >= 0) {
+                        int32_t* to = fd->tris + 3 * (int64_t)ti;
+                        to[0] = vid[r]; to[1] = b; to[2] = c;
+                    }
+                }
+                float nx_, ny_, nz_;
+                if (nin) {
+                    nx_ = nin[3 * (int64_t)vid[r]];
+                    ny_ = nin[3 * (int64_t)vid[r] + 1];
+                    nz_ = nin[3 * (int64_t)vid[r] + 2];
+                } else {
+                    vertex_normal(sc, lx, ir, H, nx_, ny_, nz_);
+                }
+                float* no = fd->normals + 3 * (int64_t)vid[r];
+                no[0] = nx_;
+                no[1] = ny_;
+                no[2] = nz_;
+            }
+        }
+    }
+}
+
+// Local segments, per tile in LDS: the similar joins of the own cells (from
+// the normals k_geom wrote), vertical runs, unions across the tile's columns,
+// the joins that leave the tile into its border slots, and every own vertex's
+// local root in the forest.  sn[l] = (normal, vertex id) for l over own cells
+// and the right column, NaN components for a vertex without a normal or an
+// empty cell.
+// 6 waves per SIMD fit at up to 1024 cells per tile without spilling
+template <int NT, int MAXC>
+__global__ __launch_bounds__(NT, (MAXC <= 1024 ? 6 : 1)) void k_cc(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
+    constexpr int NW = NT / 64;
+    constexpr int RN = (NC + NT - 1) / NT;
+    static_assert(RN * NW <= 64, "one lane per (round, wave) in the prefix scan");
+    __shared__ float4 sn[NC];
+    __shared__ int sparent[MAXC];     // union-find parent of own cells
+    __shared__ uint8_t sedge[MAXC];   // similar joins of own cells: bit 0 A (down), 1 C (right), 2 B (diagonal)
+    __shared__ int s_cnt[RN * NW];
+    __shared__ int s_misc[2];         // vertex base, own vertices
+    __shared__ int s_join[2 * MAXC];  // unions inside the tile: cell | cell << 16
+    __shared__ int s_nj;
+
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
+        const int H = fd->H, Wp = fd->Wp;
+        const float inv_h = 1.0f / (float)H;
+        const int lt = t - fd->tile_off;
+        const int k0 = lt * fd->TW;
+        const int TWe = min(fd->TW, Wp - k0);
+        const int nown = H * TWe;
+        const int nscan = nown + H;
+        const double tx = fd->thr[0], ty = fd->thr[1], tz = fd->thr[2];
+        const int cell_off = (int)fd->cell_off;
+        const bool last_tile = lt + 1 == fd->n_tiles;
+        // the tile holding the right column: the next one, or the frame's first on a closed cylinder
+        const int tn = !last_tile ? t + 1 : (fd->wrap ? fd->tile_off : -1);
+        const int step_i = NT % H;
+        const int i0 = (int)threadIdx.x - div_small(threadIdx.x, inv_h) * H;
+        __syncthreads();  // LDS of the previous tile is free
+        if (threadIdx.x == 0) s_nj = 0;
+
+        // 1. occupancy of own cells and the right column, vertex bases
+        if (wv == 0) {
+            int sv = 0;
+#pragma unroll 4
+            for (int j = fd->tile_off + lane; j < t; j += 64) sv += ws.tile_v[j];
+            sv = wave_sum(sv);
+            if (lane == 0) {
+                s_misc[0] = sv;
+                s_misc[1] = ws.tile_v[t];
+            }
+        }
         int vid[RN];
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
-            const int l = threadIdx.x + r * NT;
-            vid[r] = -1;
-            if (l < nscan && vv[r]) {
-                const int lx = l + H;
-                vid[r] = (l < nown) ? vbase + lv[r] : vbase_next + (lv[r] - own_v);
-                sc[lx].w = __int_as_float(vid[r]);
-                if (l < nown) {
-                    const float4 p = sc[lx];
-                    float* vo = fd->vertices + 3 * (int64_t)vid[r];
-                    vo[0] = p.x;
-                    vo[1] = p.y;
-                    vo[2] = p.z;
-                    if (fd->vpoint) fd->vpoint[vid[r]] = saux[l];
-                    saux[l] = tbase + ltr[r];
-                }
+            const int l = threadIdx.x + NT * r;
+            bool v = false;
+            if (l < nown) {
+                v = (ws.occ[(int64_t)t * OCC_WORDS + (l >> 6)] >> (l & 63)) & 1ull;
+            } else if (l < nscan && tn >= 0) {
+                const int j = l - nown;
+                v = (ws.occ[(int64_t)tn * OCC_WORDS + (j >> 6)] >> (j & 63)) & 1ull;
             }
+            const uint64_t bv = __ballot(v);
+            vid[r] = v ? lanes_below(bv) : -1;
+            if (lane == 0) s_cnt[r * NW + wv] = __popcll(bv);
         }
         __syncthreads();
+        const int vbase = s_misc[0], own_v = s_misc[1];
+        number_cells<NT, RN>(vid, s_cnt, vbase, last_tile ? 0 : vbase + own_v, own_v, nown, lane, wv);
 
-        // 6. triangles T_a = (p, A, B), T_b = (p, B, C) of each own anchor
-#pragma unroll
-        for (int r = 0; r < RO; ++r) {
-            const int l = threadIdx.x + r * NT;
-            if (l >= nown || !vv[r]) continue;
-            const int i = l - div_small(l, inv_h) * H;
-            if (i + 1 >= H) continue;
-            const int lx = l + H;
-            const int a = vid_of(sc[lx + 1]), b = vid_of(sc[lx + H + 1]), c = vid_of(sc[lx + H]);
-            int ti = saux[l];
-            if (a >= 0 && b >= 0) {
-                int32_t* to = fd->tris + 3 * (int64_t)ti;
-                to[0] = vid[r]; to[1] = a; to[2] = b;
-                ++ti;
-            }
-            if (b >= 0 && c >= 0) {
-                int32_t* to = fd->tris + 3 * (int64_t)ti;
-                to[0] = vid[r]; to[1] = b; to[2] = c;
-            }
-        }
-
-        // 7. normals of own cells and the right column (or the given ones), kept
-        //    in registers until every thread is done reading coordinates
-        float nrm[RN][3];
+        // 2. normals by vertex id
+        const float* __restrict__ nrm = fd->normals;
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
-            const int l = threadIdx.x + r * NT;
-            nrm[r][0] = nrm[r][1] = nrm[r][2] = 0.0f;
-            if (l < nscan && vv[r]) {
-                if (nin) {
-                    nrm[r][0] = nin[3 * (int64_t)vid[r]];
-                    nrm[r][1] = nin[3 * (int64_t)vid[r] + 1];
-                    nrm[r][2] = nin[3 * (int64_t)vid[r] + 2];
-                } else {
-                    const int i = l - div_small(l, inv_h) * H;
-                    vertex_normal(sc, l + H, i, H, nrm[r][0], nrm[r][1], nrm[r][2]);
-                }
-                if (l < nown) {
-                    float* no = fd->normals + 3 * (int64_t)vid[r];
-                    no[0] = nrm[r][0];
-                    no[1] = nrm[r][1];
-                    no[2] = nrm[r][2];
-                }
+            const int l = threadIdx.x + NT * r;
+            if (l >= nscan) continue;
+            const float q = __builtin_nanf("");
+            float4 a = make_float4(q, q, q, __int_as_float(vid[r]));
+            if (vid[r] >= 0) {
+                const float x = nrm[3 * (int64_t)vid[r]], y = nrm[3 * (int64_t)vid[r] + 1],
+                            z = nrm[3 * (int64_t)vid[r] + 2];
+                if (!(x == 0.0f && y == 0.0f && z == 0.0f)) { a.x = x; a.y = y; a.z = z; }
+            }
+            sn[l] = a;
+        }
+        __syncthreads();
+
+        // 3. similar joins of own cells (A down, C right, B diagonal; C and B into
+        //    the right column leave the tile); NaN components never compare
+        {
+            int i = i0;
+#pragma unroll
+            for (int r = 0; r < RN; ++r) {
+                const int l = threadIdx.x + NT * r;
+                const int ir = i;
+                i += step_i;
+                if (i >= H) i -= H;
+                if (l >= nown) continue;
+                const float4 a = sn[l];
+                const bool dn = ir + 1 < H;
+                int e = 0;
+                if (dn && similar(a, sn[l + 1], tx, ty, tz)) e |= 1;
+                if (similar(a, sn[l + H], tx, ty, tz)) e |= 2;
+                if (dn && similar(a, sn[l + H + 1], tx, ty, tz)) e |= 4;
+                sedge[l] = (uint8_t)e;
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RN; ++r) {
-            const int l = threadIdx.x + r * NT;
-            if (l < nscan) sc[l] = make_float4(nrm[r][0], nrm[r][1], nrm[r][2], __int_as_float(vid[r]));
-        }
-        __syncthreads();
 
-        // 8. similar joins of own cells (A down, C right, B diagonal; C and B into
-        //    the right column leave the tile)
-#pragma unroll
-        for (int r = 0; r < RO; ++r) {
-            const int l = threadIdx.x + r * NT;
-            if (l >= nown) continue;
-            const int i = l - div_small(l, inv_h) * H;
-            const float4 a = sc[l];
-            int e = 0;
-            if (i + 1 < H && similar(a, sc[l + 1], tx, ty, tz)) e |= 1;
-            if (similar(a, sc[l + H], tx, ty, tz)) e |= 2;
-            if (i + 1 < H && similar(a, sc[l + H + 1], tx, ty, tz)) e |= 4;
-            sedge[l] = (uint8_t)e;
-        }
-        __syncthreads();
-
-        // 9. vertical runs: every own cell's parent is the top cell of its run of
+        // 4. vertical runs: every own cell's parent is the top cell of its run of
         //    A joins, found with a ballot of run starts over each 64-cell chunk;
         //    a run that enters the chunk from above takes the previous chunk's head
-        int* const sparent = saux;
+        {
+            int i = i0;
 #pragma unroll
-        for (int r = 0; r < RO; ++r) {
-            const int l = threadIdx.x + r * NT;
-            bool start = true;
-            if (l < nown) {
-                const int i = l - div_small(l, inv_h) * H;
-                start = !(i >= 1 && (sedge[l - 1] & 1));
+            for (int r = 0; r < RN; ++r) {
+                const int l = threadIdx.x + NT * r;
+                const bool start = !(l < nown && i >= 1 && (sedge[l - 1] & 1));
+                i += step_i;
+                if (i >= H) i -= H;
+                const uint64_t S = __ballot(start);
+                const uint64_t mine = S & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull));
+                const int head = mine ? (l - lane) + 63 - __builtin_clzll(mine) : -1;
+                if (l < nown) sparent[l] = head;
             }
-            const uint64_t S = __ballot(start);
-            const uint64_t mine = S & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull));
-            const int head = mine ? (l - lane) + 63 - __builtin_clzll(mine) : -1;
-            if (l < nown) sparent[l] = head;
         }
         __syncthreads();
         if (64 % H != 0) {
             // a run of at most 128 cells spans at most three chunks: two passes
             for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-                for (int r = 0; r < RO; ++r) {
-                    const int l = threadIdx.x + r * NT;
+                for (int r = 0; r < RN; ++r) {
+                    const int l = threadIdx.x + NT * r;
                     if (l < nown && sparent[l] < 0) {
                         const int h = sparent[(l & ~63) - 1];
                         if (h >= 0) sparent[l] = h;
@@ -662,57 +787,72 @@ __global__ __launch_bounds__(NT) void k_tile(const BatchHeader* __restrict__ hdr
             }
         }
 
-        // 10. unions across columns.  A right (C) join is implied when the cell
-        //     above has one and both cells continue their runs downwards; a
-        //     diagonal (B) join is implied by A then C, or C then A.
+        // 5. unions across columns inside the tile.  A right (C) join is implied
+        //    when the cell above has one and both cells continue their runs
+        //    downwards; a diagonal (B) join is implied by A then C, or C then A.
+        //    The joins left are first gathered into one list (both ends as
+        //    16-bit cell indices), then spread over all threads.
+        {
+            int i = i0;
 #pragma unroll
-        for (int r = 0; r < RO; ++r) {
-            const int l = threadIdx.x + r * NT;
-            if (l >= nown) continue;
-            const int lc = div_small(l, inv_h);
-            if (lc + 1 >= TWe) continue;
-            const int i = l - lc * H;
-            const int e = sedge[l];
-            if (e & 2) {
-                const bool implied = i >= 1 && (sedge[l - 1] & 3) == 3 && (sedge[l - 1 + H] & 1);
-                if (!implied) lds_union(sparent, l, l + H);
-            }
-            if (e & 4) {
-                const bool implied = ((e & 1) && (sedge[l + 1] & 2)) || ((e & 2) && (sedge[l + H] & 1));
-                if (!implied) lds_union(sparent, l, l + H + 1);
+            for (int r = 0; r < RN; ++r) {
+                const int l = threadIdx.x + NT * r;
+                const int ir = i;
+                i += step_i;
+                if (i >= H) i -= H;
+                bool jc = false, jb = false;
+                if (l + H < nown) {   // the right neighbour column is own
+                    const int e = sedge[l];
+                    jc = (e & 2) && !(ir >= 1 && (sedge[l - 1] & 3) == 3 && (sedge[l - 1 + H] & 1));
+                    jb = (e & 4) && !(((e & 1) && (sedge[l + 1] & 2)) || ((e & 2) && (sedge[l + H] & 1)));
+                }
+                const uint64_t mc = __ballot(jc), mb = __ballot(jb);
+                const int n = __popcll(mc) + __popcll(mb);
+                if (n) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&s_nj, n);
+                    base = __shfl(base, 0, 64);
+                    if (jc) s_join[base + lanes_below(mc)] = l | ((l + H) << 16);
+                    if (jb) s_join[base + __popcll(mc) + lanes_below(mb)] = l | ((l + H + 1) << 16);
+                }
             }
         }
         __syncthreads();
+        for (int j = threadIdx.x; j < s_nj; j += NT) {
+            const int uv = s_join[j];
+            lds_union(sparent, uv & 0xffff, uv >> 16);
+        }
+        __syncthreads();
 
-        // 11. joins leaving through the right edge, with the same implication
-        //     rules (A joins of the right column from its normals), into the
-        //     tile's border slots: 2i for the C join of ring i, 2i+1 for its B join
+        // 6. joins leaving through the right edge, with the same implication
+        //    rules (A joins of the right column from its normals), into the
+        //    tile's border slots: 2i for the C join of ring i, 2i+1 for its B join
         {
             int2* const slots = ws.border + fd->border_off + (int64_t)lt * 2 * H;
             for (int i = threadIdx.x; i < H; i += NT) {
                 const int l = (TWe - 1) * H + i;
                 const int e = sedge[l];
-                const int a = cell_off + vid_of(sc[l]);
+                const int a = cell_off + vid_of(sn[l]);
                 int2 jc = make_int2(-1, -1), jb = make_int2(-1, -1);
-                if ((e & 2) && !(i >= 1 && (sedge[l - 1] & 3) == 3 && similar(sc[l - 1 + H], sc[l + H], tx, ty, tz)))
-                    jc = make_int2(a, cell_off + vid_of(sc[l + H]));
+                if ((e & 2) && !(i >= 1 && (sedge[l - 1] & 3) == 3 && similar(sn[l - 1 + H], sn[l + H], tx, ty, tz)))
+                    jc = make_int2(a, cell_off + vid_of(sn[l + H]));
                 if ((e & 4) && !(((e & 1) && (sedge[l + 1] & 2)) ||
-                                 ((e & 2) && similar(sc[l + H], sc[l + H + 1], tx, ty, tz))))
-                    jb = make_int2(a, cell_off + vid_of(sc[l + H + 1]));
+                                 ((e & 2) && similar(sn[l + H], sn[l + H + 1], tx, ty, tz))))
+                    jb = make_int2(a, cell_off + vid_of(sn[l + H + 1]));
                 slots[2 * i] = jc;
                 slots[2 * i + 1] = jb;
             }
         }
 
-        // 12. local roots: the smallest cell of each local tree (no writes while reading)
+        // 7. local roots: the smallest cell of each local tree (no writes while reading)
         int* const forest = ws.forest;
 #pragma unroll
-        for (int r = 0; r < RO; ++r) {
-            const int l = threadIdx.x + r * NT;
+        for (int r = 0; r < RN; ++r) {
+            const int l = threadIdx.x + NT * r;
             if (l >= nown || vid[r] < 0) continue;
-            int x = l;
+            int x = sparent[l];
             for (int it = 0; it < nown && sparent[x] != x; ++it) x = sparent[x];
-            forest[cell_off + vid[r]] = cell_off + vid_of(sc[x]);
+            forest[cell_off + vid[r]] = cell_off + vid_of(sn[x]);
         }
     }
 }
@@ -762,27 +902,100 @@ __device__ __forceinline__ void g_jump(int* P, int x) {
     }
 }
 
-// One thread per border slot written by k_tile.  Concurrent unions of
-// neighbouring tiles' segments link each tile's root to its left neighbour's, a
-// chain as long as the frame; after its union each thread therefore jumps the
-// two local roots it joined towards their root.
+// Union of two local roots from a border join.  The larger of the two is
+// usually still a root (the right tile's segment, not yet joined to anything):
+// then one compare-and-swap links it under the smaller, with no walk up the
+// left tile's tree.  Otherwise the general union runs.
+__device__ __forceinline__ void g_union_fast(int* P, int a, int b) {
+    const int x = max(a, b), y = min(a, b);
+    if (x == y) return;
+    if (atomicCAS(P + x, x, y) == x) return;
+    g_union(P, a, b);
+}
+
+// The tile's 2H border slots (written by k_cc), gathered into consecutive
+// lanes of one wave: returns their number; lane j < n then holds join j.
+template <int NW>
+__device__ __forceinline__ int gather_joins(const FrameDesc* fd, int t, const int2* border, int2* list,
+                                            int lane) {
+    constexpr int RS = 2 * MAX_RINGS / 64;   // slots per lane
+    const int ns = 2 * fd->H;
+    const int2* slots = border + fd->border_off + (int64_t)(t - fd->tile_off) * ns;
+    int2 ab[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+        const int j = lane + 64 * r;
+        ab[r] = j < ns ? slots[j] : make_int2(-1, -1);
+    }
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+        const uint64_t m = __ballot(ab[r].x >= 0);
+        if (ab[r].x >= 0) list[n + lanes_below(m)] = ab[r];
+        n += __popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return n;
+}
+
+// One wave per tile: the joins of its border slots, all unioned at once.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_merge(const BatchHeader* __restrict__ hdr, Workspace ws) {
-    const int n = hdr->total_border;
+    constexpr int NW = NT / 64;
+    __shared__ int2 s_j[NW][2 * MAX_RINGS];
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
     int* const P = ws.forest;
-    for (int e = blockIdx.x * NT + threadIdx.x; e < n; e += gridDim.x * NT) {
-        const int2 ab = ws.border[e];
-        if (ab.x < 0) continue;
-        const int ra = g_load(P + ab.x), rb = g_load(P + ab.y);
-        g_union(P, ra, rb);
-        g_jump(P, ra);
-        g_jump(P, rb);
+    for (int t = blockIdx.x * NW + wv; t < hdr->total_tiles; t += gridDim.x * NW) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
+        const int n = gather_joins<NW>(fd, t, ws.border, s_j[wv], lane);
+        for (int j = lane; j < n; j += 64) {
+            const int2 e = s_j[wv][j];
+            g_union_fast(P, g_load(P + e.x), g_load(P + e.y));
+        }
+        __builtin_amdgcn_wave_barrier();  // the wave's LDS list is reused by its next tile
+    }
+}
+
+// Concurrent unions of neighbouring tiles' segments link each tile's root to
+// its left neighbour's: a chain as long as the frame.  Every local root that
+// took part in a join jumps (parent := grandparent) until it points at a root;
+// all of a chain's nodes jump at once, so each covers twice the distance per
+// step and the chains collapse in about log2(length) steps.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_compress(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int NW = NT / 64;
+    __shared__ int2 s_j[NW][2 * MAX_RINGS];
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    int* const P = ws.forest;
+    for (int t = blockIdx.x * NW + wv; t < hdr->total_tiles; t += gridDim.x * NW) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
+        const int n = gather_joins<NW>(fd, t, ws.border, s_j[wv], lane);
+        for (int j = lane; j < n; j += 64) {
+            const int2 e = s_j[wv][j];
+            int x = g_load(P + e.x), y = g_load(P + e.y);
+            // both local roots jump together, one step each per pass
+            for (int it = 0; it < WALK_LIMIT; ++it) {
+                const int px = g_load(P + x), py = g_load(P + y);
+                const int gx = g_load(P + px), gy = g_load(P + py);
+                const bool mx = gx != px, my = gy != py;
+                if (mx) g_store(P + x, gx);
+                if (my) g_store(P + y, gy);
+                if (!mx && !my) break;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 // Roots.  Item b of a frame covers vertex slots [1024 b, 1024 b + 1024).  Every
-// vertex finds its segment root (walks halve the paths they take) and leaves
-// it, frame-local, in its label slot for k_resolve; the roots of each 64-slot
+// vertex finds its segment root (a read-only walk) and leaves it, frame-local,
+// in its label slot for k_resolve; the roots of each 64-slot
 // word are flagged in rootbits, each word gets the item's roots before it, and
 // the item its root count.  The item's key cells are reset for the next call.
 template <int NT>
@@ -803,16 +1016,37 @@ __global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ 
         const int v0 = lb * VITEM;
         const int64_t wbase = (int64_t)b * VITEM_WORDS;   // == vitem_off * 16 + lb * 16
         __syncthreads();  // s_w of the previous item has been read
+        // the item's walks advance together, one step per pass, so their loads overlap
+        int cur[RV];
+        uint32_t walking = 0;
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+            const int v = v0 + r * NT + threadIdx.x;
+            cur[r] = -1;
+            if (v < V) cur[r] = g_load(P + base + v);
+        }
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+            const int v = v0 + r * NT + threadIdx.x;
+            if (v < V && cur[r] != base + v) walking |= 1u << r;
+        }
+        for (int it = 0; walking && it < WALK_LIMIT; ++it) {
+            int nxt[RV];
+#pragma unroll
+            for (int r = 0; r < RV; ++r) nxt[r] = ((walking >> r) & 1u) ? g_load(P + cur[r]) : cur[r];
+#pragma unroll
+            for (int r = 0; r < RV; ++r) {
+                if (((walking >> r) & 1u) && nxt[r] == cur[r]) walking &= ~(1u << r);
+                cur[r] = nxt[r];
+            }
+        }
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int v = v0 + r * NT + threadIdx.x;
             bool isroot = false;
             if (v < V) {
-                const int g = base + v;
-                const int p = g_load(P + g);
-                const int root = (p == g) ? g : g_find(P, p);
-                fd->labels[v] = root - base;
-                isroot = root == g;
+                fd->labels[v] = cur[r] - base;
+                isroot = cur[r] == base + v;
             }
             const uint64_t bits = __ballot(isroot);
             if (lane == 0) {
@@ -914,7 +1148,7 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
     const int g_count = max(1, min(2 * cfg.grid, cfg.max_tiles));
     const int g_pblk = max(1, min(cfg.grid, cfg.max_pblk));
     const int g_vitem = max(1, min(2 * cfg.grid, cfg.max_vitems));
-    const int g_border = max(1, min(2 * cfg.grid, (cfg.max_border + NT - 1) / NT));
+    const int g_border = max(1, min(2 * cfg.grid, (cfg.max_tiles + NT / 64 - 1) / (NT / 64)));
     const int g_frames = max(1, min(cfg.grid, cfg.max_frames));
     int n = 0;
     hipError_t e = hipSuccess;
@@ -932,12 +1166,20 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
     }
     mark();
     switch (cfg.tile_cells) {
-        case 512: k_tile<NT, 512><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
-        case 2048: k_tile<NT, 2048><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
-        default: k_tile<NT, 1024><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
+        case 512: k_geom<NT, 512><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
+        case 2048: k_geom<NT, 2048><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
+        default: k_geom<NT, 1024><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
+    }
+    mark();
+    switch (cfg.tile_cells) {
+        case 512: k_cc<NT, 512><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
+        case 2048: k_cc<NT, 2048><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
+        default: k_cc<NT, 1024><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
     }
     mark();
     k_merge<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);
+    mark();
+    k_compress<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);
     mark();
     k_flatten<NT><<<g_vitem, NT, 0, stream>>>(d_hdr, ws);
     mark();

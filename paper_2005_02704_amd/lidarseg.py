@@ -30,8 +30,8 @@ LAUNCH = {"plain": LIDAR_LAUNCH_PLAIN, "batched": LIDAR_LAUNCH_BATCHED, "graph":
 EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lidar_last_error",
            "lidar_query_sizes", "lidar_mesh_segment", "lidar_ctx_set_tuning", "lidar_ctx_set_profiling",
            "lidar_ctx_stage_times")
-LIDAR_N_STAGES = 7
-STAGES = ("bin", "count", "tile", "merge", "flatten", "scan", "label")
+LIDAR_N_STAGES = 9
+STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label")
 
 
 class LidarError(RuntimeError):
