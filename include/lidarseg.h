@@ -123,9 +123,12 @@ int lidar_mesh_segment(lidar_ctx* ctx, const lidar_frame_t* frames, int32_t n_fr
                        const lidar_params_t* params, lidar_result_t* results,
                        void* stream, int32_t launch);
 
-/* Tuning of the batched forms: workgroups per stage launch (0 = automatic) and
- * the largest tile in lattice cells (512, 1024 or 2048; 0 = automatic). */
-int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_cells);
+/* Launch shape of every later call on this context: workgroups per grid-stride
+ * stage (0 = automatic: 4 per compute unit), the largest tile in lattice cells
+ * and the threads of a tile workgroup.  Supported tile shapes (cells, threads):
+ * (512, 256), (1024, 256), (2048, 256), (1024, 512), (2048, 512); 0 selects
+ * 1024 cells or 256 threads.  Results do not depend on the shape. */
+int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_cells, int32_t tile_threads);
 
 /* Per-stage timing of plain and batched launches (not of graph replays), with
  * HIP events recorded on the launch stream around each kernel of the chain.

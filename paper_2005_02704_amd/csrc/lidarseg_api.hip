@@ -57,10 +57,13 @@ struct lidar_ctx {
     bool graph_valid = false;
     size_t graph_table_bytes = 0;
     int graph_tile_cells = 0;
+    int graph_tile_threads = 0;
+    int graph_grid = 0;
 
     // tuning
     int grid_wg = 0;      // 0 = automatic
     int tile_cells = 1024;
+    int tile_threads = 256;
 
     // per-stage timing
     bool profiling = false;
@@ -222,13 +225,18 @@ void lidar_ctx_destroy(lidar_ctx* c) {
     delete c;
 }
 
-int lidar_ctx_set_tuning(lidar_ctx* c, int32_t grid_workgroups, int32_t tile_cells) {
+int lidar_ctx_set_tuning(lidar_ctx* c, int32_t grid_workgroups, int32_t tile_cells, int32_t tile_threads) {
     if (!c) return LIDAR_EINVAL;
     if (grid_workgroups < 0) return c->fail(LIDAR_EINVAL, "grid_workgroups must be >= 0");
-    if (tile_cells != 0 && tile_cells != 512 && tile_cells != 1024 && tile_cells != 2048)
-        return c->fail(LIDAR_EINVAL, "tile_cells must be 0, 512, 1024 or 2048");
+    const int cells = tile_cells ? tile_cells : 1024;
+    const int threads = tile_threads ? tile_threads : 256;
+    if (!tile_shape_supported(cells, threads))
+        return c->fail(LIDAR_EINVAL, "unsupported tile shape (cells, threads): use (512|1024|2048, 256) "
+                                     "or (1024|2048, 512)");
+    if (c->grid_wg == grid_workgroups && c->tile_cells == cells && c->tile_threads == threads) return LIDAR_OK;
     c->grid_wg = grid_workgroups;
-    c->tile_cells = tile_cells ? tile_cells : 1024;
+    c->tile_cells = cells;
+    c->tile_threads = threads;
     c->drop_graph();
     return LIDAR_OK;
 }
@@ -488,6 +496,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         for (int f = 0; f < n_frames; ++f) {
             LaunchCfg cfg;
             cfg.tile_cells = c->tile_cells;
+            cfg.tile_threads = c->tile_threads;
             cfg.max_tiles = plan[f].n_tiles;
             cfg.max_pblk = plan[f].n_pblk;
             cfg.max_vitems = plan[f].n_vitem;
@@ -525,6 +534,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         if (launch == LIDAR_LAUNCH_BATCHED) {
             LaunchCfg cfg;
             cfg.tile_cells = c->tile_cells;
+            cfg.tile_threads = c->tile_threads;
             cfg.max_tiles = (int)tiles;
             cfg.max_pblk = (int)pblk;
             cfg.max_vitems = (int)vitems;
@@ -537,8 +547,8 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         } else {
             // The captured chain uses fixed grid-stride grids and reads the batch
             // from the device table, so it serves every batch that fits the workspace.
-            if (!c->graph_valid || c->graph_table_bytes != c->table_cap ||
-                c->graph_tile_cells != c->tile_cells) {
+            if (!c->graph_valid || c->graph_table_bytes != c->table_cap || c->graph_tile_cells != c->tile_cells ||
+                c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid) {
                 c->drop_graph();
                 hipStream_t cap_stream;
                 e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
@@ -547,6 +557,8 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 if (e != hipSuccess) { hipStreamDestroy(cap_stream); return c->hip_fail(e, "hipStreamBeginCapture"); }
                 LaunchCfg cfg;
                 cfg.tile_cells = c->tile_cells;
+                cfg.tile_threads = c->tile_threads;
+            cfg.tile_threads = c->tile_threads;
                 cfg.max_tiles = (int)std::min<int64_t>(c->tiles_cap, INT32_MAX);
                 cfg.max_pblk = INT32_MAX;
                 cfg.max_vitems = (int)std::min<int64_t>(c->vitems_cap, INT32_MAX);
@@ -565,6 +577,8 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 c->graph_valid = true;
                 c->graph_table_bytes = c->table_cap;
                 c->graph_tile_cells = c->tile_cells;
+                c->graph_tile_threads = c->tile_threads;
+                c->graph_grid = auto_grid;
             }
             e = hipGraphLaunch(c->graph_exec[c->graph_next], stream);
             c->graph_next ^= 1;

@@ -79,6 +79,7 @@ inline int tile_width(int H, int tile_cells) {
 struct LaunchCfg {
     int grid;        // workgroups for grid-stride stages
     int tile_cells;  // 512, 1024 or 2048
+    int tile_threads;  // 256 or 512 threads per tile workgroup
     int max_tiles;   // tiles in the largest batch this chain may see (for exact grids)
     int max_pblk;
     int max_vitems;
@@ -87,6 +88,9 @@ struct LaunchCfg {
 };
 
 constexpr int N_STAGES = 9;  // bin, count, geom, cc, merge, compress, flatten, scan, label
+
+// Tile shapes (cells per tile, threads per tile workgroup) the kernels are built for.
+bool tile_shape_supported(int tile_cells, int tile_threads);
 
 // Enqueues the chain; when stage_events is non-null (N_STAGES + 1 events) an
 // event is recorded before the first kernel and after each kernel.

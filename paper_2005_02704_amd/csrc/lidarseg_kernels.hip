@@ -26,6 +26,8 @@
 // first vertex in the visiting order gives the same labels.  Union-find here
 // always links the larger root under the smaller, so a root is the smallest
 // vertex of its segment and the labels follow from ranking the roots.
+#include <functional>
+
 #include "lidarseg_internal.h"
 
 namespace lidarseg {
@@ -34,7 +36,6 @@ namespace {
 constexpr int WALK_LIMIT = 1 << 20;          // steps of any pointer walk (parents strictly
                                              // decrease, so a walk is far shorter; the cap
                                              // only guarantees that every loop ends)
-constexpr double EL_GUARD = 1e-5;            // rad: FP32 elevation estimate decides outside this band
 constexpr float COL_GUARD = 0.02f;           // firings: FP32 firing estimate decides outside this band
 constexpr int COL_GUARD_MAX_W = 16384;       // wider sweeps always decide the firing in FP64
 constexpr double LEN2_FLOOR = 1e-300;        // added to squared edge lengths: an absent edge
@@ -106,26 +107,56 @@ __device__ __attribute__((noinline)) int firing_fp64(double x, double y, double 
     return (int)round((atan2(y, x) - az0) / dphi);
 }
 
+// atan(q) ~= q * P(q^2) on [0, 1]: a degree-8 polynomial in q^2 fitted for this
+// library (weighted least squares on Chebyshev nodes); largest error 6e-9 rad
+// in exact arithmetic, 1e-7 rad evaluated in FP32.
+__constant__ float ATAN_P[9] = {0.99999988634662018f, -0.3333259686572097f, 0.19985904654765521f, -0.14161216713985597f, 0.10498906521530744f, -0.072347856186199572f, 0.039780477295818122f, -0.014400943859970152f, 0.0024566295904995218f};
+
+// atan2 in FP32 from the polynomial above: reduce to q = min/max in [0, 1], then
+// reflect by octant.  Error below 5e-7 rad; NaN when x = y = 0.
+__device__ __forceinline__ float atan2_poly(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float q = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+    const float s = q * q;
+    float p = ATAN_P[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) p = fmaf(p, s, ATAN_P[k]);
+    float a = q * p;
+    if (ay > ax) a = 1.57079632679489662f - a;
+    if (x < 0.0f) a = 3.14159265358979324f - a;
+    return copysignf(a, y);
+}
+
+constexpr int RING_LUT = 1024;   // buckets of the ring lookup table (tan of elevation)
+
 // ---------------------------------------------------------------------------
-// Binning and sub-sampling.  One work item = POINT_BLOCK points of one frame.
-// The cell keeps min((bits(float(r^2)) << 32) | point), i.e. the nearest return,
-// then the lower index: independent of thread order.
+// Binning and sub-sampling.  One work item = POINT_BLOCK points of one frame;
+// each workgroup takes a contiguous range of items, so its per-frame tables
+// change rarely.  The cell keeps min((bits(float(r^2)) << 32) | point), i.e.
+// the nearest return, then the lower index: independent of thread order.
 //
-// The ring and firing are FP64 decisions.  Each is first estimated in FP32; the
-// estimate is within ~1e-6 rad (atan2f error plus input rounding), so when it
-// lies farther than the guard band from every decision boundary (midpoint of
-// two ring elevations, half-integer firing) the FP64 decision is the same and
-// is not computed.  Inside a band the FP64 expression decides.
+// The ring and firing are FP64 decisions (nearest ring elevation; firing =
+// round((atan2(y, x) - az0) / dphi)).  Each is first decided in FP32: the ring
+// from t = z / sqrt(x^2 + y^2) against the tangents of the midpoints between
+// ring elevations (tan is increasing, so the comparison is the same), through a
+// lookup table over t; the firing from a polynomial atan2.  The estimates are
+// within a few 1e-7 (relative for t, radians for the azimuth), so when they lie
+// farther than a guard band from every decision boundary the FP64 decision is
+// the same and is not computed.  Inside a band the FP64 expression decides.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int PPT = POINT_BLOCK / NT;  // points per thread per item
     __shared__ double s_elev[MAX_RINGS];
-    __shared__ double s_mid[MAX_RINGS];    // s_mid[i]: midpoint of rings i and i+1
+    __shared__ float s_T[MAX_RINGS];       // s_T[i]: tan of the midpoint of rings i and i+1 (descending)
+    __shared__ uint8_t s_lut[RING_LUT];    // ring at the lower edge of each t bucket
+    __shared__ float s_lo, s_inv;          // t at the first bucket's lower edge, buckets per unit t
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
     const int nb = hdr->total_pblk;
+    const int per = (nb + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int b0 = blockIdx.x * per, b1 = min(nb, b0 + per);
     int cur = -1;
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    for (int b = b0; b < b1; ++b) {
         const int f = frame_of<&FrameDesc::pblk_off>(F, nf, b);
         const FrameDesc* fd = F + f;
         const int H = fd->H;
@@ -133,7 +164,24 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
             __syncthreads();
             for (int i = threadIdx.x; i < H; i += NT) s_elev[i] = ws.elev[fd->elev_off + i];
             __syncthreads();
-            for (int i = threadIdx.x; i + 1 < H; i += NT) s_mid[i] = 0.5 * (s_elev[i] + s_elev[i + 1]);
+            for (int i = threadIdx.x; i + 1 < H; i += NT) s_T[i] = (float)tan(0.5 * (s_elev[i] + s_elev[i + 1]));
+            __syncthreads();
+            // buckets span the boundaries with a margin; outside them the table's
+            // end values (ring H-1 below, 0 above) are exact
+            const float thi = H > 1 ? s_T[0] : 0.0f, tlo = H > 1 ? s_T[H - 2] : 0.0f;
+            const float pad = 0.01f * (thi - tlo) + 1e-3f;
+            const float lo = tlo - pad, inv = (float)RING_LUT / (thi - tlo + 2.0f * pad);
+            for (int k = threadIdx.x; k < RING_LUT; k += NT) {
+                const float e = lo + (float)k / inv;
+                // rings whose upper boundary lies above e: first i with s_T[i] <= e
+                int a = 0, c = H - 1;
+                while (a < c) {
+                    const int m = (a + c) >> 1;
+                    if (s_T[m] <= e) c = m; else a = m + 1;
+                }
+                s_lut[k] = (uint8_t)a;
+            }
+            if (threadIdx.x == 0) { s_lo = lo; s_inv = inv; }
             __syncthreads();
             cur = f;
         }
@@ -142,6 +190,7 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
         const float az0f = (float)az0;
         const float inv_dphif = (float)(1.0 / dphi);
         const bool col_fast = W <= COL_GUARD_MAX_W;
+        const float lo = s_lo, inv = s_inv;
         const float* __restrict__ xyz = fd->xyz;
         unsigned long long* keys = reinterpret_cast<unsigned long long*>(ws.keys + fd->cell_off);
         const int64_t p0 = (int64_t)(b - fd->pblk_off) * POINT_BLOCK + threadIdx.x;
@@ -168,15 +217,22 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
             const double r2 = rho2 + z * z;
             if (r2 < rmin2 || r2 > rmax2) continue;
 
-            const double elf = (double)atan2f(zf, sqrtf(xf * xf + yf * yf));
-            int ring = nearest_ring(s_elev, H, elf);
-            if ((ring > 0 && fabs(elf - s_mid[ring - 1]) < EL_GUARD) ||
-                (ring + 1 < H && fabs(elf - s_mid[ring]) < EL_GUARD))
-                ring = ring_fp64(s_elev, H, z, rho2);
+            // ring: t against the midpoint tangents, through the bucket table
+            const float t = zf * __builtin_amdgcn_rsqf(fmaf(xf, xf, yf * yf));
+            int ring;
+            bool exact = !isfinite(t);
+            if (!exact) {
+                const float bf = fminf(fmaxf((t - lo) * inv, 0.0f), (float)(RING_LUT - 1));
+                ring = s_lut[(int)bf];
+                for (int k = 0; k < MAX_RINGS && ring > 0 && t > s_T[ring - 1]; ++k) --ring;
+                exact = (ring > 0 && fabsf(t - s_T[ring - 1]) <= 2e-6f * fabsf(s_T[ring - 1]) + 1e-7f) ||
+                        (ring + 1 < H && fabsf(t - s_T[ring]) <= 2e-6f * fabsf(s_T[ring]) + 1e-7f);
+            }
+            if (exact) ring = ring_fp64(s_elev, H, z, rho2);
 
             // |az0| <= 2 pi, so the rounded firing lies in [-2W, 2W)
             int j;
-            const float jff = (atan2f(yf, xf) - az0f) * inv_dphif;
+            const float jff = (atan2_poly(yf, xf) - az0f) * inv_dphif;
             if (col_fast && fabsf(jff - floorf(jff) - 0.5f) > COL_GUARD)
                 j = (int)floorf(jff + 0.5f);
             else
@@ -431,9 +487,9 @@ __device__ __forceinline__ void number_cells(int (&vid)[RN], const int* s_cnt, i
 // l = lx - H runs over own cells and then the right column; thread x handles
 // l = x + r * NT in round r, so every 64-cell chunk is one wave's round.
 // Writes vertices, vertex_point, triangles and normals.
-// 5 waves per SIMD at up to 1024 cells per tile
+// 5 waves per SIMD at up to 4 cells per thread
 template <int NT, int MAXC>
-__global__ __launch_bounds__(NT, (MAXC <= 1024 ? 5 : 1)) void k_geom(const BatchHeader* __restrict__ hdr, Workspace ws) {
+__global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int XC = MAXC + 3 * MAX_RINGS;  // coordinate cells incl. halo
     constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
     constexpr int RX = (XC + NT - 1) / NT;
@@ -648,9 +704,9 @@ __global__ __launch_bounds__(NT, (MAXC <= 1024 ? 5 : 1)) void k_geom(const Batch
 // local root in the forest.  sn[l] = (normal, vertex id) for l over own cells
 // and the right column, NaN components for a vertex without a normal or an
 // empty cell.
-// 6 waves per SIMD fit at up to 1024 cells per tile without spilling
+// 6 waves per SIMD fit at up to 4 cells per thread without spilling
 template <int NT, int MAXC>
-__global__ __launch_bounds__(NT, (MAXC <= 1024 ? 6 : 1)) void k_cc(const BatchHeader* __restrict__ hdr, Workspace ws) {
+__global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
     constexpr int NW = NT / 64;
     constexpr int RN = (NC + NT - 1) / NT;
@@ -1139,44 +1195,51 @@ __global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ 
     }
 }
 
+// The three tile kernels for one tile shape (TT threads, MAXC cells per tile).
+template <int TT, int MAXC>
+void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_tiles, int g_cc, hipStream_t stream,
+                        const std::function<void()>& mark) {
+    k_count<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
+    mark();
+    k_geom<TT, MAXC><<<g_tiles, TT, 0, stream>>>(d_hdr, ws);
+    mark();
+    k_cc<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
+    mark();
+}
+
 }  // namespace
+
+bool tile_shape_supported(int tile_cells, int tile_threads) {
+    return (tile_threads == 256 && (tile_cells == 512 || tile_cells == 1024 || tile_cells == 2048)) ||
+           (tile_threads == 512 && (tile_cells == 1024 || tile_cells == 2048));
+}
 
 hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const LaunchCfg& cfg,
                         hipStream_t stream, hipEvent_t* ev) {
     constexpr int NT = 256;
     const int g_tiles = max(1, min(cfg.grid, cfg.max_tiles));
-    const int g_count = max(1, min(2 * cfg.grid, cfg.max_tiles));
+    const int g_cc = max(1, min(2 * cfg.grid, cfg.max_tiles));
     const int g_pblk = max(1, min(cfg.grid, cfg.max_pblk));
     const int g_vitem = max(1, min(2 * cfg.grid, cfg.max_vitems));
     const int g_border = max(1, min(2 * cfg.grid, (cfg.max_tiles + NT / 64 - 1) / (NT / 64)));
     const int g_frames = max(1, min(cfg.grid, cfg.max_frames));
     int n = 0;
     hipError_t e = hipSuccess;
-    auto mark = [&]() {
+    const std::function<void()> mark = [&]() {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[n], stream);
         ++n;
     };
     mark();
     k_bin<NT><<<g_pblk, NT, 0, stream>>>(d_hdr, ws);
     mark();
-    switch (cfg.tile_cells) {
-        case 512: k_count<NT, 512><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
-        case 2048: k_count<NT, 2048><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
-        default: k_count<NT, 1024><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
+    const int shape = cfg.tile_cells * 4 + cfg.tile_threads / 256;
+    switch (shape) {
+        case 512 * 4 + 1: launch_tile_stages<256, 512>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
+        case 2048 * 4 + 1: launch_tile_stages<256, 2048>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
+        case 1024 * 4 + 2: launch_tile_stages<512, 1024>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
+        case 2048 * 4 + 2: launch_tile_stages<512, 2048>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
+        default: launch_tile_stages<256, 1024>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
     }
-    mark();
-    switch (cfg.tile_cells) {
-        case 512: k_geom<NT, 512><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
-        case 2048: k_geom<NT, 2048><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
-        default: k_geom<NT, 1024><<<g_tiles, NT, 0, stream>>>(d_hdr, ws); break;
-    }
-    mark();
-    switch (cfg.tile_cells) {
-        case 512: k_cc<NT, 512><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
-        case 2048: k_cc<NT, 2048><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
-        default: k_cc<NT, 1024><<<g_count, NT, 0, stream>>>(d_hdr, ws); break;
-    }
-    mark();
     k_merge<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);
     mark();
     k_compress<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);

@@ -89,7 +89,7 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(lidar_params_t), ctypes.POINTER(lidar_result_t),
                                      P, ctypes.c_int32]
     L.lidar_mesh_segment.restype = ctypes.c_int
-    L.lidar_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    L.lidar_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lidar_ctx_set_tuning.restype = ctypes.c_int
     L.lidar_ctx_set_profiling.argtypes = [P, ctypes.c_int32]
     L.lidar_ctx_set_profiling.restype = ctypes.c_int
@@ -189,8 +189,8 @@ class LidarContext:
         except Exception:
             pass
 
-    def set_tuning(self, grid_workgroups: int = 0, tile_cells: int = 0):
-        rc = self._L.lidar_ctx_set_tuning(self._h, int(grid_workgroups), int(tile_cells))
+    def set_tuning(self, grid_workgroups: int = 0, tile_cells: int = 0, tile_threads: int = 0):
+        rc = self._L.lidar_ctx_set_tuning(self._h, int(grid_workgroups), int(tile_cells), int(tile_threads))
         self._check(rc)
 
     def set_profiling(self, enable: bool):

@@ -85,13 +85,15 @@ def test_launch_forms_and_tiles_agree(ctx):
             for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
                 assert np.array_equal(a[k], b[k]), (launch, k)
             assert a["counts"] == b["counts"]
-    for tc in (512, 2048, 1024):
-        ctx.set_tuning(0, tc)
-        got = run_gpu(ctx, items, launch="batched")
-        for a, b in zip(ref, got):
-            for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
-                assert np.array_equal(a[k], b[k]), (tc, k)
-    ctx.set_tuning(0, 0)
+    for grid, tc, th in ((0, 512, 256), (0, 2048, 256), (0, 1024, 512), (0, 2048, 512), (300, 1024, 256),
+                         (4096, 1024, 256)):
+        ctx.set_tuning(grid, tc, th)
+        for launch in ("batched", "graph"):
+            got = run_gpu(ctx, items, launch=launch)
+            for a, b in zip(ref, got):
+                for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
+                    assert np.array_equal(a[k], b[k]), (grid, tc, th, launch, k)
+    ctx.set_tuning(0, 0, 0)
     for f, g in zip(frames, ref):
         r = run_oracle(f.xyz, f.sensor, 1)
         check_geometry(g, r)
