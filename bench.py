@@ -104,7 +104,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile-cells", type=int, default=0, help="0 = library default")
+    ap.add_argument("--tile-cells", type=int, default=0, help="0 = autotuned table / library default")
+    ap.add_argument("--tile-threads", type=int, default=0, help="0 = autotuned table / library default")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per batched stage, 0 = library default")
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
@@ -143,9 +144,17 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = lp.LidarContext(0)
-    ctx.set_tuning(args.grid, args.tile_cells)
     params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2))
     geos = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, 1, 1, f.sensor.az0) for f in frames]
+    if args.grid or args.tile_cells or args.tile_threads:
+        shape = {"grid": args.grid, "tile_cells": args.tile_cells, "tile_threads": args.tile_threads}
+        ctx.set_tuning(args.grid, args.tile_cells, args.tile_threads)
+        shape_src = "command line"
+    else:
+        from paper_2005_02704_amd import autotune
+        shape = autotune.apply(ctx, geos)
+        shape_src = f"autotuned table, class {autotune.batch_class(geos)}"
+    log(f"launch shape {shape} ({shape_src})")
     inputs = [(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)]
     outs = [lp.Outputs(g, dev) for g in geos]
     prep = ctx.prepare(inputs, params, outs)
@@ -253,7 +262,7 @@ def main():
         "config": {"workload": f"batched {args.frames} uneven street sweeps (rings 16/32/64/128, "
                                f"azimuth 1024/2048/4096, s=1)", "frames": args.frames,
                    "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
-                   "launch": "graph", "seed": args.seed},
+                   "launch": "graph", "seed": args.seed, "launch_shape": shape, "launch_shape_source": shape_src},
         "forms": {
             "graph": {"points_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4)},
             "batched": {"points_per_s": round(N / (ms_batched * 1e-3), 1), "ms_per_step": round(ms_batched, 4)},

@@ -79,13 +79,24 @@ typedef struct {
                                       V must be this frame's vertex count. */
 } lidar_frame_t;
 
+/* Similarity tests of lidar_params_t.predicate. */
+#define LIDAR_PRED_COMPONENTS 0  /* Algorithm 1: every normal component differs by < I, J, K */
+#define LIDAR_PRED_COSINE 1      /* n_p . n_q > cos_min (dot product of the FP32 normals,
+                                    summed in FP64 as (x x' + y y') + z z') */
+
 /* Parameters (Section 2, Mesh Construction "within range of the Lidar";
- * Algorithm 1 thresholds I, J, K, which Section 3 sets to 0.2 each). */
+ * Algorithm 1 thresholds I, J, K, which Section 3 sets to 0.2 each; Section 2,
+ * Segmentation, last paragraph: optional removal of segments with too few
+ * points). */
 typedef struct {
     double r_min, r_max;  /* valid range window in metres, 0 <= r_min <= r_max */
     double thr[3];        /* I, J, K > 0: a neighbour joins when every component of
                              the normal differs by strictly less (exact FP64 difference
                              of the FP32 normals) */
+    int32_t predicate;    /* LIDAR_PRED_COMPONENTS (default) or LIDAR_PRED_COSINE */
+    int32_t min_segment;  /* >= 2: labels carried by fewer vertices become 0 (the count
+                             K is unchanged); 0 or 1: keep every segment */
+    double cos_min;       /* LIDAR_PRED_COSINE threshold, in [-1, 1) */
 } lidar_params_t;
 
 /* Caller-owned outputs of one frame, sized by lidar_query_sizes().  Written
@@ -97,8 +108,14 @@ typedef struct {
     int32_t* triangles;     /* device [T][3]: vertex indices, each oriented so that
                                (v1-v0) x (v2-v0) points away from the sensor */
     int32_t* vertex_point;  /* device [V] or NULL: input index of each vertex */
-    int64_t* counts;        /* device [3]: V, T, K; -1 if the frame's work failed on the
-                               device (a bounded wait expired; outputs are then invalid) */
+    int64_t* counts;        /* device [3]: V, T, K */
+    int32_t* point_labels;  /* device [n_points] or NULL: every input point's label
+                               (Section 2, Segmentation: the points the sub-sampling
+                               skipped take the label of the nearest vertex of their
+                               ring along the sweep, by firing distance -- around the
+                               cylinder when it is closed -- the earlier firing on a
+                               tie); 0 for a point that is not used or whose ring has
+                               no vertex */
 } lidar_result_t;
 
 /* Create a context on HIP device `device`.  The context owns its device
@@ -136,8 +153,9 @@ int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_c
  * geom (numbering, mesh triangles, normals), cc (similar joins, local
  * segments), merge (segments across tiles), compress (pointer jumping on the
  * merged segments), flatten (segment roots), scan (rank bases of the roots),
- * label.  Enabling costs one event per kernel. */
-#define LIDAR_N_STAGES 9
+ * label, post (segment removal and point labels; zero time when neither is
+ * asked for).  Enabling costs one event per kernel. */
+#define LIDAR_N_STAGES 10
 int lidar_ctx_set_profiling(lidar_ctx* ctx, int32_t enable);
 /* Waits for the profiled calls, then writes the summed milliseconds and the
  * number of timed launches of each stage (arrays of LIDAR_N_STAGES; launches

@@ -53,6 +53,17 @@ def lib():
         L.oracle_normals.restype = i64
         L.oracle_labels.argtypes = [i32, i32, i32, P, P, P, P, P]
         L.oracle_labels.restype = i64
+        L.oracle_labels_pred.argtypes = [i32, i32, i32, P, P, P, i32, P, f64, P]
+        L.oracle_labels_pred.restype = i64
+        L.oracle_prune.argtypes = [P, i64, i64, i32]
+        L.oracle_prune.restype = None
+        L.oracle_point_cells.argtypes = [P, i64, i32, i32, P, f64, f64, f64, P, P]
+        L.oracle_point_cells.restype = None
+        L.oracle_backfill.argtypes = [i64, P, P, i32, i32, i32, i32, P, P]
+        L.oracle_backfill.restype = None
+        L.oracle_mesh_segment_ex.argtypes = [P, i64, i32, i32, i32, i32, P, f64, f64, f64, i32, P, f64, i32,
+                                             P, P, P, P, P, P, P, P]
+        L.oracle_mesh_segment_ex.restype = ctypes.c_int
         L.oracle_mesh_segment.argtypes = [P, i64, i32, i32, i32, i32, P, f64, f64, f64, P,
                                           P, P, P, P, P, P, P]
         L.oracle_mesh_segment.restype = ctypes.c_int
@@ -107,15 +118,45 @@ def normals(H, Wp, wrap, cell_xyz, valid):
     return n, h
 
 
-def labels(H, Wp, wrap, valid, has_normal, normals32, thr=(0.2, 0.2, 0.2)):
-    """Step 5 (Algorithm 1) on a grid: labels per cell (0 = empty cell), K."""
+def labels(H, Wp, wrap, valid, has_normal, normals32, thr=(0.2, 0.2, 0.2), predicate=0, cos_min=0.0):
+    """Step 5 (Algorithm 1) on a grid: labels per cell (0 = empty cell), K.
+    predicate 0: component-wise thresholds thr; 1: n_p . n_q > cos_min."""
     valid = _c(valid, np.uint8)
     has_normal = _c(has_normal, np.uint8)
     normals32 = _c(normals32, np.float32).reshape(-1, 3)
     thr = _c(thr, np.float64)
     out = np.empty(H * Wp, dtype=np.int32)
-    K = lib().oracle_labels(H, Wp, wrap, _p(valid), _p(has_normal), _p(normals32), _p(thr), _p(out))
+    K = lib().oracle_labels_pred(H, Wp, wrap, _p(valid), _p(has_normal), _p(normals32), int(predicate),
+                                 _p(thr), float(cos_min), _p(out))
     return out, int(K)
+
+
+def prune(vertex_labels, K, min_size):
+    """Step 6a: labels carried by fewer than min_size vertices become 0."""
+    out = _c(vertex_labels, np.int32).copy()
+    lib().oracle_prune(_p(out), out.shape[0], int(K), int(min_size))
+    return out
+
+
+def point_cells(xyz, H, W, elev, az0=0.0, r_min=1.0, r_max=60.0):
+    """Every point's full-resolution (ring, firing), -1 for a point that is not used."""
+    xyz = _c(xyz, np.float32).reshape(-1, 3)
+    elev = _c(elev, np.float64)
+    ring = np.empty(xyz.shape[0], np.int32)
+    firing = np.empty(xyz.shape[0], np.int32)
+    lib().oracle_point_cells(_p(xyz), xyz.shape[0], H, W, _p(elev), az0, r_min, r_max, _p(ring), _p(firing))
+    return ring, firing
+
+
+def backfill(ring, firing, H, W, s, wrap, cell_label):
+    """Step 6b: every point's label from the nearest vertex of its ring along the sweep.
+    cell_label: [H * W/s] label of each cell's vertex, -1 for an empty cell."""
+    ring = _c(ring, np.int32)
+    firing = _c(firing, np.int32)
+    cell_label = _c(cell_label, np.int32)
+    out = np.empty(ring.shape[0], np.int32)
+    lib().oracle_backfill(ring.shape[0], _p(ring), _p(firing), H, W, s, wrap, _p(cell_label), _p(out))
+    return out
 
 
 @dataclass
@@ -126,16 +167,19 @@ class Result:
     triangles: np.ndarray     # int32 [T,3]
     vertex_point: np.ndarray  # int32 [V]
     normals64: np.ndarray     # float64 [V,3]
+    point_labels: np.ndarray | None = None  # int32 [N] (when asked for)
+    K: int | None = None      # label count before segment removal
 
     @property
     def counts(self):
-        return (self.vertices.shape[0], self.triangles.shape[0],
-                int(self.labels.max()) if self.labels.size else 0)
+        K = self.K if self.K is not None else (int(self.labels.max()) if self.labels.size else 0)
+        return (self.vertices.shape[0], self.triangles.shape[0], K)
 
 
 def mesh_segment(xyz, H, W, s, elev, *, az0=0.0, r_min=1.0, r_max=60.0, thr=(0.2, 0.2, 0.2),
-                 wrap=1) -> Result:
-    """The whole path on one sweep (compact outputs in vertex order)."""
+                 wrap=1, predicate=0, cos_min=0.0, min_segment=0, point_labels=False) -> Result:
+    """The whole path on one sweep (compact outputs in vertex order); with
+    point_labels, every input point's label as well (step 6b)."""
     xyz = _c(xyz, np.float32).reshape(-1, 3)
     elev = _c(elev, np.float64)
     thr = _c(thr, np.float64)
@@ -147,13 +191,16 @@ def mesh_segment(xyz, H, W, s, elev, *, az0=0.0, r_min=1.0, r_max=60.0, thr=(0.2
     T = np.empty((2 * cells + 1, 3), np.int32)
     VP = np.empty(cells, np.int32)
     N64 = np.empty((cells, 3), np.float64)
+    PL = np.empty(max(xyz.shape[0], 1), np.int32) if point_labels else None
     cnt = np.zeros(3, np.int64)
-    rc = lib().oracle_mesh_segment(_p(xyz), xyz.shape[0], H, W, s, wrap, _p(elev), az0, r_min, r_max,
-                                   _p(thr), _p(V), _p(Nn), _p(L), _p(T), _p(VP), _p(cnt), _p(N64))
+    rc = lib().oracle_mesh_segment_ex(_p(xyz), xyz.shape[0], H, W, s, wrap, _p(elev), az0, r_min, r_max,
+                                      int(predicate), _p(thr), float(cos_min), int(min_segment), _p(V), _p(Nn),
+                                      _p(L), _p(T), _p(VP), _p(cnt), _p(N64), _p(PL) if PL is not None else None)
     if rc != 0:
         raise ValueError("oracle_mesh_segment: bad arguments")
     v, t = int(cnt[0]), int(cnt[1])
-    return Result(V[:v].copy(), Nn[:v].copy(), L[:v].copy(), T[:t].copy(), VP[:v].copy(), N64[:v].copy())
+    return Result(V[:v].copy(), Nn[:v].copy(), L[:v].copy(), T[:t].copy(), VP[:v].copy(), N64[:v].copy(),
+                  PL[:xyz.shape[0]].copy() if PL is not None else None, int(cnt[2]))
 
 
 def mesh_segment_frame(frame, s=1, **kw) -> Result:

@@ -10,6 +10,8 @@
  *   3. mesh by joining lattice neighbours; the map M              -- Section 2, Mesh Construction
  *   4. per-vertex normal from weighted consecutive cross products -- Section 2, Normal Estimation
  *   5. Algorithm 1: depth-first label propagation                 -- Section 2, Algorithm 1
+ *   6. labels for the points the sub-sampling skipped, and removal of
+ *      segments with too few points (optional)                    -- Section 2, Segmentation
  *
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg load
  * this library.  It shares no source, header or table with the GPU library.
@@ -31,7 +33,15 @@
  *     triangle (or a zero sum) has no normal, and no edge touching it is similar;
  *   - the label counter is incremented after each seed's flood;
  *   - the similarity test reads the normal map N as stored (FP32) and takes
- *     each component difference exactly in FP64, strict '<'.
+ *     each component difference exactly in FP64, strict '<'; the optional
+ *     cosine test is n_p . n_q > cos_min with the dot product summed in FP64 as
+ *     (x x' + y y') + z z';
+ *   - a point's label is that of the nearest vertex (sampled, kept point) in its
+ *     ring along the sweep, by firing distance (around the cylinder when it is
+ *     closed), the earlier firing on a tie; 0 if its ring has no vertex or the
+ *     point was not used;
+ *   - a segment has "too few points" when fewer than min_segment vertices carry
+ *     its label; its vertices (and the points that took its label) get label 0.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -o liblidar_oracle.so lidar_oracle.c -lm
  */
@@ -66,7 +76,41 @@ static int64_t neighbour_cell(int32_t H, int32_t Wp, int32_t wrap, int32_t i, in
 
 /* ------------------------------------------------------------------------ */
 /* Steps 1-2: binning and sub-sampling.
- * cell_point[c] = index of the point kept in cell c, or -1.  Returns #occupied. */
+ * The lattice position of one point: its ring (nearest elevation, the upper ring
+ * on a tie) and firing (nearest azimuth sample, round half away from zero,
+ * modulo W), both decided in FP64.  Returns 0 when the point is not used
+ * (non-finite, or outside the range window), 1 otherwise; r2 receives x^2+y^2+z^2. */
+static int bin_decide(const float* q, int32_t H, int32_t W, const double* elev, double az0,
+                      double rmin2, double rmax2, int32_t* ring_out, int64_t* firing_out, double* r2_out)
+{
+    double x = q[0], y = q[1], z = q[2];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return 0;
+    double rho2 = x * x + y * y;
+    double r2 = rho2 + z * z;
+    if (r2 < rmin2 || r2 > rmax2) return 0;                /* "within range of the Lidar" */
+
+    /* ring: nearest elevation, first (upper) ring on a tie */
+    double el = atan2(z, sqrt(rho2));
+    int32_t ring = 0;
+    double best = fabs(el - elev[0]);
+    for (int32_t i = 1; i < H; ++i) {
+        double d = fabs(el - elev[i]);
+        if (d < best) { best = d; ring = i; }
+    }
+
+    /* firing: nearest azimuth sample of the spin */
+    double dphi = 2.0 * M_PI / (double)W;
+    double jf = (atan2(y, x) - az0) / dphi;
+    int64_t j = (int64_t)round(jf);
+    j %= W;
+    if (j < 0) j += W;
+    *ring_out = ring;
+    *firing_out = j;
+    *r2_out = r2;
+    return 1;
+}
+
+/* cell_point[c] = index of the point kept in cell c, or -1.  Returns #occupied. */
 int64_t oracle_bin(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
                    const double* elev, double az0, double r_min, double r_max,
                    int64_t* cell_point)
@@ -76,32 +120,15 @@ int64_t oracle_bin(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
     float* best_r2 = (float*)malloc(sizeof(float) * (size_t)(ncell > 0 ? ncell : 1));
     const double rmin2 = r_min * r_min;
     const double rmax2 = r_max * r_max;
-    const double dphi = 2.0 * M_PI / (double)W;
     int64_t occupied = 0;
 
     for (int64_t c = 0; c < ncell; ++c) cell_point[c] = -1;
 
     for (int64_t p = 0; p < n; ++p) {
-        double x = xyz[3 * p + 0], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
-        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) continue;
-        double rho2 = x * x + y * y;
-        double r2 = rho2 + z * z;
-        if (r2 < rmin2 || r2 > rmax2) continue;           /* "within range of the Lidar" */
-
-        /* ring: nearest elevation, first (upper) ring on a tie */
-        double el = atan2(z, sqrt(rho2));
-        int32_t ring = 0;
-        double best = fabs(el - elev[0]);
-        for (int32_t i = 1; i < H; ++i) {
-            double d = fabs(el - elev[i]);
-            if (d < best) { best = d; ring = i; }
-        }
-
-        /* firing: nearest azimuth sample of the spin */
-        double jf = (atan2(y, x) - az0) / dphi;
-        int64_t j = (int64_t)round(jf);
-        j %= W;
-        if (j < 0) j += W;
+        int32_t ring;
+        int64_t j;
+        double r2;
+        if (!bin_decide(xyz + 3 * p, H, W, elev, az0, rmin2, rmax2, &ring, &j, &r2)) continue;
         if (j % s != 0) continue;                           /* sub-sampling */
         int64_t c = (j / s) * H + ring;
 
@@ -114,6 +141,24 @@ int64_t oracle_bin(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
     }
     free(best_r2);
     return occupied;
+}
+
+/* Every point's ring and firing (full resolution, before sub-sampling), or
+ * ring = firing = -1 for a point that is not used. */
+void oracle_point_cells(const float* xyz, int64_t n, int32_t H, int32_t W, const double* elev,
+                        double az0, double r_min, double r_max, int32_t* ring, int32_t* firing)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int32_t i;
+        int64_t j;
+        double r2;
+        if (bin_decide(xyz + 3 * p, H, W, elev, az0, r_min * r_min, r_max * r_max, &i, &j, &r2)) {
+            ring[p] = i;
+            firing[p] = (int32_t)j;
+        } else {
+            ring[p] = firing[p] = -1;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -231,12 +276,25 @@ int64_t oracle_normals(int32_t H, int32_t Wp, int32_t wrap, const float* cell_xy
 /* ------------------------------------------------------------------------ */
 /* Step 5: Algorithm 1 (Section 2, Segmentation by Surface Homogeneity).
  * labels[c] = 0 for empty cells, else 1..K.  Seeds are visited in firing order;
- * a popped vertex p floods each unlabelled mesh neighbour q whose normal
- * components all differ from p's by less than thr (strict), both having normals.
+ * a popped vertex p floods each unlabelled mesh neighbour q when both have
+ * normals and the test holds: pred 0 -- every normal component differs by less
+ * than thr (strict); pred 1 -- n_p . n_q > cos_min.
  * normals32: the stored normal map N, [cells][3] float.  Returns K. */
-int64_t oracle_labels(int32_t H, int32_t Wp, int32_t wrap, const uint8_t* valid,
-                      const uint8_t* has_normal, const float* normals32, const double* thr,
-                      int32_t* labels)
+static int similar_normals(const float* a, const float* b, int32_t pred, const double* thr, double cos_min)
+{
+    if (pred == 1) {
+        double dot = ((double)a[0] * (double)b[0] + (double)a[1] * (double)b[1]) + (double)a[2] * (double)b[2];
+        return dot > cos_min;
+    }
+    double dx = fabs((double)a[0] - (double)b[0]);
+    double dy = fabs((double)a[1] - (double)b[1]);
+    double dz = fabs((double)a[2] - (double)b[2]);
+    return dx < thr[0] && dy < thr[1] && dz < thr[2];
+}
+
+int64_t oracle_labels_pred(int32_t H, int32_t Wp, int32_t wrap, const uint8_t* valid,
+                           const uint8_t* has_normal, const float* normals32, int32_t pred,
+                           const double* thr, double cos_min, int32_t* labels)
 {
     const int64_t ncell = (int64_t)H * Wp;
     int64_t* stack = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ncell + 1));
@@ -257,10 +315,7 @@ int64_t oracle_labels(int32_t H, int32_t Wp, int32_t wrap, const uint8_t* valid,
                     int64_t q = neighbour_cell(H, Wp, wrap, pi, pk, t);
                     if (q < 0 || !valid[q] || labels[q] != 0) continue;
                     if (!has_normal[p] || !has_normal[q]) continue;
-                    double dx = fabs((double)normals32[3 * p] - (double)normals32[3 * q]);
-                    double dy = fabs((double)normals32[3 * p + 1] - (double)normals32[3 * q + 1]);
-                    double dz = fabs((double)normals32[3 * p + 2] - (double)normals32[3 * q + 2]);
-                    if (dx < thr[0] && dy < thr[1] && dz < thr[2]) {
+                    if (similar_normals(normals32 + 3 * p, normals32 + 3 * q, pred, thr, cos_min)) {
                         labels[q] = label;
                         stack[sp++] = q;
                     }
@@ -272,19 +327,87 @@ int64_t oracle_labels(int32_t H, int32_t Wp, int32_t wrap, const uint8_t* valid,
     return (int64_t)label - 1;
 }
 
+int64_t oracle_labels(int32_t H, int32_t Wp, int32_t wrap, const uint8_t* valid,
+                      const uint8_t* has_normal, const float* normals32, const double* thr,
+                      int32_t* labels)
+{
+    return oracle_labels_pred(H, Wp, wrap, valid, has_normal, normals32, 0, thr, 0.0, labels);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 6a (Section 2, Segmentation, last paragraph): optional removal of
+ * segments with too few points.  labels: [V] vertex labels 1..K; a label carried
+ * by fewer than min_size vertices becomes 0.  min_size <= 1 keeps everything. */
+void oracle_prune(int32_t* labels, int64_t V, int64_t K, int32_t min_size)
+{
+    if (min_size <= 1) return;
+    int64_t* size = (int64_t*)calloc((size_t)K + 1, sizeof(int64_t));
+    for (int64_t v = 0; v < V; ++v) size[labels[v]] += 1;
+    for (int64_t v = 0; v < V; ++v)
+        if (labels[v] > 0 && size[labels[v]] < min_size) labels[v] = 0;
+    free(size);
+}
+
+/* Step 6b (Section 2, Segmentation): the points the sub-sampling skipped get
+ * the label of the nearest labelled point along the horizontal sweep.  For each
+ * point with ring i and firing j (ring < 0: not used -> label 0), every vertex
+ * of ring i is a candidate: sampled column k at firing k s, at distance
+ * |j - k s| (around the cylinder, min(d, W - d), when it is closed); the
+ * nearest wins, the one at firing j - d (the earlier along the sweep) on a tie.
+ * cell_label: [H * W/s] label of each cell's vertex, -1 for an empty cell. */
+void oracle_backfill(int64_t n, const int32_t* ring, const int32_t* firing, int32_t H, int32_t W,
+                     int32_t s, int32_t wrap, const int32_t* cell_label, int32_t* point_labels)
+{
+    const int32_t Wp = W / s;
+    for (int64_t p = 0; p < n; ++p) {
+        point_labels[p] = 0;
+        if (ring[p] < 0) continue;
+        const int32_t i = ring[p], j = firing[p];
+        int64_t best_d = -1;
+        int32_t best_label = 0;
+        int best_left = 0;
+        for (int32_t k = 0; k < Wp; ++k) {
+            const int32_t lab = cell_label[(int64_t)k * H + i];
+            if (lab < 0) continue;
+            const int64_t jk = (int64_t)k * s;
+            int64_t d_left, d_right;          /* the vertex before / after the point along the sweep */
+            if (wrap) {
+                d_left = ((int64_t)j - jk + W) % W;
+                d_right = (jk - (int64_t)j + W) % W;
+            } else {
+                d_left = jk <= j ? j - jk : -1;
+                d_right = jk >= j ? jk - j : -1;
+            }
+            /* its distance: the shorter way round; reached from the left on a tie */
+            int64_t d;
+            int left;
+            if (d_left >= 0 && (d_right < 0 || d_left <= d_right)) { d = d_left; left = 1; }
+            else { d = d_right; left = 0; }
+            if (best_d < 0 || d < best_d || (d == best_d && left && !best_left)) {
+                best_d = d; best_label = lab; best_left = left;
+            }
+        }
+        point_labels[p] = best_label;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* The whole path on one sweep.  Outputs are compact, in vertex (firing) order:
  *   vertices [V][3] float (the kept input point, bit-exact)
  *   normals  [V][3] float (FP64 result rounded once; zero = no normal)
- *   labels   [V] int32 (1..K), triangles [T][3] int32, vertex_point [V] int32
- *   counts   {V, T, K}
+ *   labels   [V] int32 (1..K, 0 after segment removal), triangles [T][3] int32,
+ *   vertex_point [V] int32, counts {V, T, K}
+ *   point_labels [n] int32 (optional): every input point's label (step 6b)
+ * pred / cos_min select the similarity test (Algorithm 1's component test, or
+ * the cosine test); min_segment > 1 removes smaller segments (step 6a).
  * Capacity: V <= H*(W/s), T <= 2*H*(W/s).  normals64 (optional, [V][3]) receives
  * the unrounded FP64 normals.  Returns 0, or -1 on a bad argument. */
-int oracle_mesh_segment(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
-                        int32_t wrap, const double* elev, double az0, double r_min,
-                        double r_max, const double* thr, float* vertices, float* normals,
-                        int32_t* labels, int32_t* triangles, int32_t* vertex_point,
-                        int64_t* counts, double* normals64)
+int oracle_mesh_segment_ex(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
+                           int32_t wrap, const double* elev, double az0, double r_min,
+                           double r_max, int32_t pred, const double* thr, double cos_min,
+                           int32_t min_segment, float* vertices, float* normals, int32_t* labels,
+                           int32_t* triangles, int32_t* vertex_point, int64_t* counts,
+                           double* normals64, int32_t* point_labels)
 {
     if (H < 1 || W < 1 || s < 1 || W % s != 0) return -1;
     const int32_t Wp = W / s;
@@ -306,7 +429,7 @@ int oracle_mesh_segment(const float* xyz, int64_t n, int32_t H, int32_t W, int32
     }
     oracle_normals(H, Wp, wrap, cxyz, valid, n64, hasn);
     for (int64_t q = 0; q < 3 * ncell; ++q) n32[q] = (float)n64[q];
-    int64_t K = oracle_labels(H, Wp, wrap, valid, hasn, n32, thr, lab);
+    int64_t K = oracle_labels_pred(H, Wp, wrap, valid, hasn, n32, pred, thr, cos_min, lab);
     int64_t T = oracle_triangles(H, Wp, wrap, valid, triangles);
 
     int64_t V = 0;
@@ -321,9 +444,31 @@ int oracle_mesh_segment(const float* xyz, int64_t n, int32_t H, int32_t W, int32
         if (vertex_point) vertex_point[V] = (int32_t)cell_point[c];
         ++V;
     }
+    oracle_prune(labels, V, K, min_segment);
+    if (point_labels) {
+        /* the cell labels after removal, then every point from its ring and firing */
+        int64_t v = 0;
+        for (int64_t c = 0; c < ncell; ++c) lab[c] = valid[c] ? labels[v++] : -1;
+        int32_t* pr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        int32_t* pf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        oracle_point_cells(xyz, n, H, W, elev, az0, r_min, r_max, pr, pf);
+        oracle_backfill(n, pr, pf, H, W, s, wrap, lab, point_labels);
+        free(pr); free(pf);
+    }
     counts[0] = V;
     counts[1] = T;
     counts[2] = K;
     free(cell_point); free(valid); free(hasn); free(cxyz); free(n64); free(n32); free(lab);
     return 0;
+}
+
+int oracle_mesh_segment(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
+                        int32_t wrap, const double* elev, double az0, double r_min,
+                        double r_max, const double* thr, float* vertices, float* normals,
+                        int32_t* labels, int32_t* triangles, int32_t* vertex_point,
+                        int64_t* counts, double* normals64)
+{
+    return oracle_mesh_segment_ex(xyz, n, H, W, s, wrap, elev, az0, r_min, r_max, 0, thr, 0.0, 0,
+                                  vertices, normals, labels, triangles, vertex_point, counts, normals64,
+                                  NULL);
 }

@@ -41,6 +41,11 @@ struct lidar_ctx {
     int64_t vitems_cap = 0;
     int2* border = nullptr;
     int64_t border_cap = 0;
+    int32_t* pcell = nullptr;     // per input point record (point labels)
+    int64_t pcell_cap = 0;
+    int32_t* cvid = nullptr;      // per cell vertex id (point labels)
+    int32_t* segsize = nullptr;   // per label size (segment removal)
+    int64_t aux_cells_cap = 0;    // capacity of cvid and segsize
     char* d_table = nullptr;      // descriptor tables + elevations
     char* h_table[2] = {nullptr, nullptr};  // pinned staging of d_table, used alternately
     size_t table_cap = 0;
@@ -59,6 +64,7 @@ struct lidar_ctx {
     int graph_tile_cells = 0;
     int graph_tile_threads = 0;
     int graph_grid = 0;
+    bool graph_post = false;
 
     // tuning
     int grid_wg = 0;      // 0 = automatic
@@ -105,6 +111,9 @@ struct lidar_ctx {
         ws.wprefix = wprefix;
         ws.vitem_roots = vitem_roots;
         ws.border = border;
+        ws.pcell = pcell;
+        ws.cvid = cvid;
+        ws.segsize = segsize;
         ws.elev = reinterpret_cast<const double*>(d_table);
         return ws;
     }
@@ -217,6 +226,9 @@ void lidar_ctx_destroy(lidar_ctx* c) {
     if (c->wprefix) (void)hipFree(c->wprefix);
     if (c->vitem_roots) (void)hipFree(c->vitem_roots);
     if (c->border) (void)hipFree(c->border);
+    if (c->pcell) (void)hipFree(c->pcell);
+    if (c->cvid) (void)hipFree(c->cvid);
+    if (c->segsize) (void)hipFree(c->segsize);
     if (c->d_table) (void)hipFree(c->d_table);
     for (int b = 0; b < 2; ++b) {
         if (c->h_table[b]) (void)hipHostFree(c->h_table[b]);
@@ -286,11 +298,18 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     for (int q = 0; q < 3; ++q)
         if (!(std::isfinite(params->thr[q]) && params->thr[q] > 0.0))
             return c->fail(LIDAR_EINVAL, "thresholds must be finite and > 0");
+    if (params->predicate != LIDAR_PRED_COMPONENTS && params->predicate != LIDAR_PRED_COSINE)
+        return c->fail(LIDAR_EINVAL, "unknown predicate");
+    if (params->predicate == LIDAR_PRED_COSINE && !(std::isfinite(params->cos_min) && params->cos_min >= -1.0 &&
+                                                     params->cos_min < 1.0))
+        return c->fail(LIDAR_EINVAL, "cos_min must lie in [-1, 1)");
+    if (params->min_segment < 0) return c->fail(LIDAR_EINVAL, "min_segment must be >= 0");
 
     // ---- plan ----
     std::vector<FramePlan> plan(n_frames);
     int64_t cells = 0, border_slots = 0, elev_total = 0;
-    int64_t tiles = 0, pblk = 0, vitems = 0;
+    int64_t tiles = 0, pblk = 0, vitems = 0, labelled_points = 0, max_points_f = 0;
+    bool any_point_labels = false;
     int64_t max_cells = 0, max_tiles_f = 0, max_pblk_f = 0, max_vitem_f = 0, max_border_f = 0;
     for (int f = 0; f < n_frames; ++f) {
         const lidar_frame_t& fr = frames[f];
@@ -299,6 +318,14 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         if (rc) return c->fail(rc, "frame " + std::to_string(f) + ": " + msg);
         if (fr.n_points < 0 || fr.n_points > INT32_MAX)
             return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": n_points out of range");
+        if (results[f].point_labels) {
+            if ((int64_t)fr.sensor->n_rings * fr.sensor->n_azimuth > INT32_MAX)
+                return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) +
+                                                 ": point labels need n_rings * n_azimuth below 2^31");
+            any_point_labels = true;
+            labelled_points += fr.n_points;
+            max_points_f = std::max<int64_t>(max_points_f, fr.n_points);
+        }
         if (fr.n_points > 0 && !fr.xyz)
             return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": xyz is NULL");
         const lidar_result_t& r = results[f];
@@ -330,8 +357,11 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     }
     if (tiles > INT32_MAX || pblk > INT32_MAX || cells > MAX_BATCH_CELLS || border_slots > INT32_MAX)
         return c->fail(LIDAR_EINVAL, "batch too large (at most 2^31 - 1024 lattice cells in one call)");
+    const bool prune = params->min_segment > 1;
+    const bool post = prune || any_point_labels;
     // plain launches run the frames one after another on shared workspace offsets
     if (launch == LIDAR_LAUNCH_PLAIN) {
+        labelled_points = max_points_f;
         cells = max_cells;
         tiles = max_tiles_f;
         vitems = max_vitem_f;
@@ -355,7 +385,9 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
 
     // ---- capacity ----
     const bool grow = cells > c->keys_cap || tiles > c->tiles_cap || vitems > c->vitems_cap ||
-                      border_slots > c->border_cap || table_bytes > c->table_cap;
+                      border_slots > c->border_cap || table_bytes > c->table_cap ||
+                      (any_point_labels && labelled_points > c->pcell_cap) ||
+                      ((any_point_labels || prune) && cells > c->aux_cells_cap);
     if (grow) {
         int rc = c->wait_idle();
         if (rc) return rc;
@@ -406,6 +438,29 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             }
             c->vitems_cap = cap;
         }
+        if (any_point_labels && labelled_points > c->pcell_cap) {
+            if (c->pcell) (void)hipFree(c->pcell);
+            c->pcell = nullptr;
+            const int64_t cap = std::max<int64_t>(labelled_points, c->pcell_cap * 3 / 2);
+            if (hipMalloc(&c->pcell, sizeof(int32_t) * std::max<int64_t>(cap, 1)) != hipSuccess) {
+                c->pcell_cap = 0;
+                return c->fail(LIDAR_ENOMEM, "cannot allocate point records");
+            }
+            c->pcell_cap = cap;
+        }
+        if ((any_point_labels || prune) && cells > c->aux_cells_cap) {
+            if (c->cvid) (void)hipFree(c->cvid);
+            if (c->segsize) (void)hipFree(c->segsize);
+            c->cvid = nullptr;
+            c->segsize = nullptr;
+            const int64_t cap = std::max<int64_t>(cells, c->aux_cells_cap * 3 / 2);
+            if (hipMalloc(&c->cvid, sizeof(int32_t) * cap) != hipSuccess ||
+                hipMalloc(&c->segsize, sizeof(int32_t) * cap) != hipSuccess) {
+                c->aux_cells_cap = 0;
+                return c->fail(LIDAR_ENOMEM, "cannot allocate per-cell label arrays");
+            }
+            c->aux_cells_cap = cap;
+        }
         if (border_slots > c->border_cap) {
             if (c->border) (void)hipFree(c->border);
             c->border = nullptr;
@@ -442,8 +497,8 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     }
     char* const htab = c->h_table[buf];
     std::memset(htab, 0, table_bytes);
-    auto fill_desc = [&](FrameDesc& d, int f, int64_t cell_off, int64_t border_off, int tile_off, int pblk_off,
-                         int vitem_off, int elev_off) {
+    auto fill_desc = [&](FrameDesc& d, int f, int64_t cell_off, int64_t border_off, int64_t pt_off, int tile_off,
+                         int pblk_off, int vitem_off, int elev_off) {
         const lidar_frame_t& fr = frames[f];
         const lidar_result_t& r = results[f];
         const FramePlan& p = plan[f];
@@ -458,6 +513,11 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         d.n_points = fr.n_points;
         d.cell_off = cell_off;
         d.border_off = border_off;
+        d.pt_off = pt_off;
+        d.point_labels = r.point_labels;
+        d.pred = params->predicate;
+        d.min_seg = params->min_segment;
+        d.cos_min = params->cos_min;
         d.H = p.H; d.W = p.W; d.s = p.s; d.Wp = p.Wp; d.wrap = p.wrap; d.TW = p.TW;
         d.n_tiles = p.n_tiles; d.tile_off = tile_off;
         d.n_pblk = p.n_pblk; d.pblk_off = pblk_off;
@@ -485,10 +545,11 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             h->total_pblk = plan[f].n_pblk;
             h->total_vitems = plan[f].n_vitem;
             h->total_border = (int)plan[f].border_slots;
+            h->post = (prune || results[f].point_labels) ? 1 : 0;
             FrameDesc* d = h->frames();
             const size_t elev_byte = off + sizeof(BatchHeader) + desc_bytes;
             // frames run one after another on the stream, so they share workspace offsets
-            fill_desc(*d, f, 0, 0, 0, 0, 0, (int)(elev_byte / 8));
+            fill_desc(*d, f, 0, 0, 0, 0, 0, 0, (int)(elev_byte / 8));
             off += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
         }
         e = hipMemcpyAsync(c->d_table, htab, table_bytes, hipMemcpyHostToDevice, stream);
@@ -502,6 +563,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.max_vitems = plan[f].n_vitem;
             cfg.max_border = (int)plan[f].border_slots;
             cfg.max_frames = 1;
+            cfg.post = prune || results[f].point_labels;
             cfg.grid = std::max(std::max(plan[f].n_tiles, plan[f].n_pblk), plan[f].n_vitem);
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table + offs[f]), ws, cfg, stream, ev);
@@ -514,14 +576,16 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         h->total_pblk = (int)pblk;
         h->total_vitems = (int)vitems;
         h->total_border = (int)border_slots;
+        h->post = post ? 1 : 0;
         FrameDesc* d = h->frames();
         const size_t elev_base = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) / 8;
-        int64_t cell_off = 0, border_off = 0;
+        int64_t cell_off = 0, border_off = 0, pt_off = 0;
         int tile_off = 0, pblk_off = 0, vitem_off = 0, elev_off = (int)elev_base;
         for (int f = 0; f < n_frames; ++f) {
-            fill_desc(d[f], f, cell_off, border_off, tile_off, pblk_off, vitem_off, elev_off);
+            fill_desc(d[f], f, cell_off, border_off, pt_off, tile_off, pblk_off, vitem_off, elev_off);
             cell_off += plan[f].cells;
             border_off += plan[f].border_slots;
+            if (results[f].point_labels) pt_off += frames[f].n_points;
             tile_off += plan[f].n_tiles;
             pblk_off += plan[f].n_pblk;
             vitem_off += plan[f].n_vitem;
@@ -540,6 +604,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.max_vitems = (int)vitems;
             cfg.max_border = (int)border_slots;
             cfg.max_frames = n_frames;
+            cfg.post = post;
             cfg.grid = auto_grid;
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
@@ -548,7 +613,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             // The captured chain uses fixed grid-stride grids and reads the batch
             // from the device table, so it serves every batch that fits the workspace.
             if (!c->graph_valid || c->graph_table_bytes != c->table_cap || c->graph_tile_cells != c->tile_cells ||
-                c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid) {
+                c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid || c->graph_post != post) {
                 c->drop_graph();
                 hipStream_t cap_stream;
                 e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
@@ -564,6 +629,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 cfg.max_vitems = (int)std::min<int64_t>(c->vitems_cap, INT32_MAX);
                 cfg.max_border = (int)std::min<int64_t>(c->border_cap, INT32_MAX);
                 cfg.max_frames = INT32_MAX;
+                cfg.post = post;
                 cfg.grid = auto_grid;
                 hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
                 e = hipStreamEndCapture(cap_stream, &c->graph);
@@ -579,6 +645,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 c->graph_tile_cells = c->tile_cells;
                 c->graph_tile_threads = c->tile_threads;
                 c->graph_grid = auto_grid;
+                c->graph_post = post;
             }
             e = hipGraphLaunch(c->graph_exec[c->graph_next], stream);
             c->graph_next ^= 1;

@@ -27,16 +27,22 @@ struct FrameDesc {
     int32_t* tris;
     int32_t* vpoint;          // may be null
     int64_t* counts;
+    int32_t* point_labels;    // may be null: every input point's label
     int64_t n_points;
     int64_t cell_off;         // first cell of this frame in the key grid and the forest
     int64_t border_off;       // first border slot (int2) of this frame: 2H slots per tile
+    int64_t pt_off;           // first per-point record of this frame (when point_labels)
     int32_t H, W, s, Wp, wrap, TW;
     int32_t n_tiles, tile_off;
     int32_t n_pblk, pblk_off;
     int32_t n_vitem, vitem_off;  // labelling items (VITEM vertex slots each); words at vitem_off * VITEM_WORDS
-    int32_t elev_off, pad0;
+    int32_t elev_off;
+    int32_t pred;             // similarity test: 0 components (Algorithm 1), 1 cosine
+    int32_t min_seg;          // >= 2: segments with fewer vertices get label 0
+    int32_t pad0;
     double az0, dphi, rmin2, rmax2;
     double thr[3];
+    double cos_min;
 };
 
 struct BatchHeader {
@@ -45,7 +51,7 @@ struct BatchHeader {
     int32_t total_pblk;
     int32_t total_vitems;
     int32_t total_border;     // border slots of the batch
-    int32_t pad;
+    int32_t post;             // 1: some frame asks for segment removal or point labels
     FrameDesc* frames() { return reinterpret_cast<FrameDesc*>(this + 1); }
 };
 static_assert(sizeof(BatchHeader) == 24, "header size");
@@ -67,6 +73,10 @@ struct Workspace {
                           // of the frame before it
     int2* border;         // per tile and ring: the similar C and B joins that leave the
                           // tile through its right edge (forest positions), or (-1, -1)
+    int32_t* pcell;       // per input point (pt_off + p): j * H + i of its full-resolution
+                          // ring i and firing j, -1 if not used (point labels only)
+    int32_t* cvid;        // per cell (cell_off + cell): its vertex id, -1 if empty (point labels only)
+    int32_t* segsize;     // per label (cell_off + label - 1): vertices carrying it (segment removal)
     const double* elev;   // ring elevations, per frame at elev_off
 };
 
@@ -85,9 +95,10 @@ struct LaunchCfg {
     int max_vitems;
     int max_border;  // border slots
     int max_frames;
+    bool post;       // launch the segment-removal / point-label stage
 };
 
-constexpr int N_STAGES = 9;  // bin, count, geom, cc, merge, compress, flatten, scan, label
+constexpr int N_STAGES = 10;  // bin, count, geom, cc, merge, compress, flatten, scan, label, post
 
 // Tile shapes (cells per tile, threads per tile workgroup) the kernels are built for.
 bool tile_shape_supported(int tile_cells, int tile_threads);

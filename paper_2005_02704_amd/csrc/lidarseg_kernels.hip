@@ -18,7 +18,8 @@
 //   k_compress pointer jumping on the segments joined across borders
 //   k_flatten  every vertex to its segment root; roots flagged; key cells reset
 //   k_scan     per frame: roots before each labelling item (their rank base)
-//   k_resolve  label = 1 + rank of the vertex's root
+//   k_resolve  label = 1 + rank of the vertex's root; segment sizes
+//   k_post     (when asked for) segment removal and every input point's label  [Segmentation, last paragraph]
 //
 // Algorithm 1 floods through neighbours whose normal components differ by less
 // than the thresholds; that test is symmetric, so the flood's label classes are
@@ -207,49 +208,55 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
                 pz[r] = xyz[3 * p + 2];
             }
         }
+        int32_t* const pcell = fd->point_labels ? ws.pcell + fd->pt_off : nullptr;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
             const int64_t p = p0 + r * NT;
             const float xf = px[r], yf = py[r], zf = pz[r];
-            if (!(isfinite(xf) && isfinite(yf) && isfinite(zf))) continue;
-            const double x = xf, y = yf, z = zf;
-            const double rho2 = x * x + y * y;   // products of floats are exact in FP64
-            const double r2 = rho2 + z * z;
-            if (r2 < rmin2 || r2 > rmax2) continue;
+            int rec = -1;   // j * H + i of a used point (full resolution), for its label later
+            do {
+                if (!(isfinite(xf) && isfinite(yf) && isfinite(zf))) break;
+                const double x = xf, y = yf, z = zf;
+                const double rho2 = x * x + y * y;   // products of floats are exact in FP64
+                const double r2 = rho2 + z * z;
+                if (r2 < rmin2 || r2 > rmax2) break;
 
-            // ring: t against the midpoint tangents, through the bucket table
-            const float t = zf * __builtin_amdgcn_rsqf(fmaf(xf, xf, yf * yf));
-            int ring;
-            bool exact = !isfinite(t);
-            if (!exact) {
-                const float bf = fminf(fmaxf((t - lo) * inv, 0.0f), (float)(RING_LUT - 1));
-                ring = s_lut[(int)bf];
-                for (int k = 0; k < MAX_RINGS && ring > 0 && t > s_T[ring - 1]; ++k) --ring;
-                exact = (ring > 0 && fabsf(t - s_T[ring - 1]) <= 2e-6f * fabsf(s_T[ring - 1]) + 1e-7f) ||
-                        (ring + 1 < H && fabsf(t - s_T[ring]) <= 2e-6f * fabsf(s_T[ring]) + 1e-7f);
-            }
-            if (exact) ring = ring_fp64(s_elev, H, z, rho2);
+                // ring: t against the midpoint tangents, through the bucket table
+                const float t = zf * __builtin_amdgcn_rsqf(fmaf(xf, xf, yf * yf));
+                int ring = 0;
+                bool exact = !isfinite(t);
+                if (!exact) {
+                    const float bf = fminf(fmaxf((t - lo) * inv, 0.0f), (float)(RING_LUT - 1));
+                    ring = s_lut[(int)bf];
+                    for (int k = 0; k < MAX_RINGS && ring > 0 && t > s_T[ring - 1]; ++k) --ring;
+                    exact = (ring > 0 && fabsf(t - s_T[ring - 1]) <= 2e-6f * fabsf(s_T[ring - 1]) + 1e-7f) ||
+                            (ring + 1 < H && fabsf(t - s_T[ring]) <= 2e-6f * fabsf(s_T[ring]) + 1e-7f);
+                }
+                if (exact) ring = ring_fp64(s_elev, H, z, rho2);
 
-            // |az0| <= 2 pi, so the rounded firing lies in [-2W, 2W)
-            int j;
-            const float jff = (atan2_poly(yf, xf) - az0f) * inv_dphif;
-            if (col_fast && fabsf(jff - floorf(jff) - 0.5f) > COL_GUARD)
-                j = (int)floorf(jff + 0.5f);
-            else
-                j = firing_fp64(x, y, az0, dphi);
-            if (j < 0) j += W;
-            if (j < 0) j += W;
-            if (j >= W) j -= W;
-            if (j >= W) j -= W;
-            int k = j;
-            if (s > 1) {
-                k = j / s;
-                if (k * s != j) continue;
-            }
-            const int64_t c = (int64_t)k * H + ring;
-            const unsigned long long key =
-                ((unsigned long long)__float_as_uint((float)r2) << 32) | (unsigned long long)(uint32_t)p;
-            atomicMin(keys + c, key);
+                // |az0| <= 2 pi, so the rounded firing lies in [-2W, 2W)
+                int j;
+                const float jff = (atan2_poly(yf, xf) - az0f) * inv_dphif;
+                if (col_fast && fabsf(jff - floorf(jff) - 0.5f) > COL_GUARD)
+                    j = (int)floorf(jff + 0.5f);
+                else
+                    j = firing_fp64(x, y, az0, dphi);
+                if (j < 0) j += W;
+                if (j < 0) j += W;
+                if (j >= W) j -= W;
+                if (j >= W) j -= W;
+                rec = j * H + ring;
+                int k = j;
+                if (s > 1) {
+                    k = j / s;
+                    if (k * s != j) break;
+                }
+                const int64_t c = (int64_t)k * H + ring;
+                const unsigned long long key =
+                    ((unsigned long long)__float_as_uint((float)r2) << 32) | (unsigned long long)(uint32_t)p;
+                atomicMin(keys + c, key);
+            } while (false);
+            if (pcell && p < np) pcell[p] = rec;
         }
     }
 }
@@ -365,12 +372,23 @@ __device__ __forceinline__ void lds_union(int* P, int a, int b) {
 }
 
 // Algorithm 1's test: both vertices have normals and every component differs by
-// strictly less than its threshold.  Differences of two floats are exact in
-// FP64.  A vertex without a normal carries NaN components here, which fail
-// every comparison.
-__device__ __forceinline__ bool similar(float4 a, float4 b, double tx, double ty, double tz) {
-    return fabs((double)a.x - (double)b.x) < tx && fabs((double)a.y - (double)b.y) < ty &&
-           fabs((double)a.z - (double)b.z) < tz;
+// strictly less than its threshold (differences of two floats are exact in
+// FP64); or, as the alternative test, the dot product of the two normals
+// exceeds cos_min.  A vertex without a normal carries NaN components here,
+// which fail every comparison.
+struct SimTest {
+    int pred;               // 0: components (Algorithm 1), 1: cosine
+    double tx, ty, tz, cmin;
+};
+
+__device__ __forceinline__ bool similar(float4 a, float4 b, const SimTest& q) {
+    if (q.pred) {
+        // products of floats are exact in FP64; the sum is (x x' + y y') + z z'
+        const double d = ((double)a.x * (double)b.x + (double)a.y * (double)b.y) + (double)a.z * (double)b.z;
+        return d > q.cmin;
+    }
+    return fabs((double)a.x - (double)b.x) < q.tx && fabs((double)a.y - (double)b.y) < q.ty &&
+           fabs((double)a.z - (double)b.z) < q.tz;
 }
 
 // FP64 reciprocal, reciprocal square root and square root: the hardware estimate
@@ -637,7 +655,16 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
         }
         number_cells<NT, RN>(vid, s_cnt, vbase, last_tile ? 0 : vbase + own_v, own_v, nown, lane, wv);
 
-        // 5. vertices, their points and triangle starts
+        // 5. vertices, their points and triangle starts (and, for point labels,
+        //    every own cell's vertex id)
+        if (fd->point_labels) {
+            int32_t* const cvid = ws.cvid + fd->cell_off + (int64_t)k0 * H;
+#pragma unroll
+            for (int r = 0; r < RN; ++r) {
+                const int l = threadIdx.x + NT * r;
+                if (l < nown) cvid[l] = vid[r];
+            }
+        }
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
             const int l = threadIdx.x + NT * r;
@@ -731,7 +758,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
         const int TWe = min(fd->TW, Wp - k0);
         const int nown = H * TWe;
         const int nscan = nown + H;
-        const double tx = fd->thr[0], ty = fd->thr[1], tz = fd->thr[2];
+        SimTest sim;
+        sim.pred = fd->pred;
+        sim.tx = fd->thr[0];
+        sim.ty = fd->thr[1];
+        sim.tz = fd->thr[2];
+        sim.cmin = fd->cos_min;
         const int cell_off = (int)fd->cell_off;
         const bool last_tile = lt + 1 == fd->n_tiles;
         // the tile holding the right column: the next one, or the frame's first on a closed cylinder
@@ -802,9 +834,9 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
                 const float4 a = sn[l];
                 const bool dn = ir + 1 < H;
                 int e = 0;
-                if (dn && similar(a, sn[l + 1], tx, ty, tz)) e |= 1;
-                if (similar(a, sn[l + H], tx, ty, tz)) e |= 2;
-                if (dn && similar(a, sn[l + H + 1], tx, ty, tz)) e |= 4;
+                if (dn && similar(a, sn[l + 1], sim)) e |= 1;
+                if (similar(a, sn[l + H], sim)) e |= 2;
+                if (dn && similar(a, sn[l + H + 1], sim)) e |= 4;
                 sedge[l] = (uint8_t)e;
             }
         }
@@ -890,10 +922,10 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
                 const int e = sedge[l];
                 const int a = cell_off + vid_of(sn[l]);
                 int2 jc = make_int2(-1, -1), jb = make_int2(-1, -1);
-                if ((e & 2) && !(i >= 1 && (sedge[l - 1] & 3) == 3 && similar(sn[l - 1 + H], sn[l + H], tx, ty, tz)))
+                if ((e & 2) && !(i >= 1 && (sedge[l - 1] & 3) == 3 && similar(sn[l - 1 + H], sn[l + H], sim)))
                     jc = make_int2(a, cell_off + vid_of(sn[l + H]));
                 if ((e & 4) && !(((e & 1) && (sedge[l + 1] & 2)) ||
-                                 ((e & 2) && similar(sn[l + H], sn[l + H + 1], tx, ty, tz))))
+                                 ((e & 2) && similar(sn[l + H], sn[l + H + 1], sim))))
                     jb = make_int2(a, cell_off + vid_of(sn[l + H + 1]));
                 slots[2 * i] = jc;
                 slots[2 * i + 1] = jb;
@@ -1125,6 +1157,10 @@ __global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ 
         const int c1 = min(v0 + VITEM, fd->H * fd->Wp);
         uint64_t* keys = ws.keys + fd->cell_off;
         for (int c = v0 + threadIdx.x; c < c1; c += NT) keys[c] = KEY_EMPTY;
+        if (fd->min_seg > 1) {
+            int32_t* size = ws.segsize + fd->cell_off;
+            for (int c = v0 + threadIdx.x; c < c1; c += NT) size[c] = 0;
+        }
     }
 }
 
@@ -1185,11 +1221,95 @@ __global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ 
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int v = v0 + r * NT + threadIdx.x;
+            int lab = -1;
             if (v < V) {
                 const int root = fd->labels[v];
                 const int64_t w = wframe + (root >> 6);
                 const uint64_t below = ws.rootbits[w] & ((1ull << (root & 63)) - 1ull);
-                fd->labels[v] = 1 + ibase[root / VITEM] + (int)ws.wprefix[w] + __popcll(below);
+                lab = 1 + ibase[root / VITEM] + (int)ws.wprefix[w] + __popcll(below);
+                fd->labels[v] = lab;
+            }
+            if (fd->min_seg > 1) {
+                // segment sizes: one atomic per distinct label of the wave
+                int32_t* size = ws.segsize + fd->cell_off - 1;
+                uint64_t todo = __ballot(lab > 0);
+                while (todo) {
+                    const int leader = __builtin_ctzll(todo);
+                    const int L = __shfl(lab, leader, 64);
+                    const uint64_t same = __ballot(lab == L);
+                    if ((int)(threadIdx.x & 63) == leader) atomicAdd(size + L, (int)__popcll(same));
+                    todo &= ~same;
+                }
+            }
+        }
+    }
+}
+
+// The label of input point p from its full-resolution cell (ring i, firing j):
+// that of the nearest vertex of ring i along the sweep.  Sampled columns are
+// visited outwards from j, the nearer side first (the earlier firing on a tie),
+// until one holds a vertex; around the cylinder when it is closed, at most W'
+// columns in all.  A label carried by fewer than min_seg vertices reads as 0.
+__device__ __forceinline__ int backfill_label(const FrameDesc* fd, const Workspace& ws, int rec) {
+    if (rec < 0) return 0;
+    const int H = fd->H, s = fd->s, Wp = fd->Wp, wrap = fd->wrap;
+    const int i = rec % H, j = rec / H;
+    const int32_t* cvid = ws.cvid + fd->cell_off + i;
+    int kl = j / s, kr = kl + 1;
+    int dl = j - kl * s, dr = kr * s - j;
+    int vid = -1;
+    for (int n = 0; n < Wp; ++n) {
+        const bool lok = wrap || kl >= 0, rok = wrap || kr < Wp;
+        if (!lok && !rok) break;
+        const bool left = lok && (!rok || dl <= dr);
+        int k = left ? kl : kr;
+        if (k < 0) k += Wp;
+        if (k >= Wp) k -= Wp;
+        const int v = cvid[(int64_t)k * H];
+        if (v >= 0) { vid = v; break; }
+        if (left) { --kl; dl += s; } else { ++kr; dr += s; }
+    }
+    if (vid < 0) return 0;
+    const int lab = fd->labels[vid];
+    if (fd->min_seg > 1 && lab > 0 && ws.segsize[fd->cell_off + lab - 1] < fd->min_seg) return 0;
+    return lab;
+}
+
+// Segment removal (Section 2, Segmentation, last paragraph: labels carried by
+// fewer than min_seg vertices become 0) over labelling items, and every input
+// point's label (the points the sub-sampling skipped take the label of the
+// nearest vertex of their ring along the sweep) over point blocks.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_post(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int RV = VITEM / NT;
+    constexpr int PPT = POINT_BLOCK / NT;
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    const int nv = hdr->total_vitems;
+    for (int b = blockIdx.x; b < nv + hdr->total_pblk; b += gridDim.x) {
+        if (b < nv) {
+            const FrameDesc* fd = F + frame_of<&FrameDesc::vitem_off>(F, nf, b);
+            if (fd->min_seg <= 1) continue;
+            const int V = (int)max<int64_t>(fd->counts[0], 0);
+            const int v0 = (b - fd->vitem_off) * VITEM;
+            const int32_t* size = ws.segsize + fd->cell_off - 1;
+#pragma unroll
+            for (int r = 0; r < RV; ++r) {
+                const int v = v0 + r * NT + threadIdx.x;
+                if (v < V) {
+                    const int lab = fd->labels[v];
+                    if (lab > 0 && size[lab] < fd->min_seg) fd->labels[v] = 0;
+                }
+            }
+        } else {
+            const int pb = b - nv;
+            const FrameDesc* fd = F + frame_of<&FrameDesc::pblk_off>(F, nf, pb);
+            if (!fd->point_labels) continue;
+            const int64_t p0 = (int64_t)(pb - fd->pblk_off) * POINT_BLOCK + threadIdx.x;
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+                const int64_t p = p0 + r * NT;
+                if (p < fd->n_points) fd->point_labels[p] = backfill_label(fd, ws, ws.pcell[fd->pt_off + p]);
             }
         }
     }
@@ -1249,6 +1369,12 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
     k_scan<NT><<<g_frames, NT, 0, stream>>>(d_hdr, ws);
     mark();
     k_resolve<NT><<<g_vitem, NT, 0, stream>>>(d_hdr, ws);
+    mark();
+    if (cfg.post) {
+        const int64_t items = (int64_t)cfg.max_vitems + cfg.max_pblk;
+        const int g_post = (int)(items < 2 * (int64_t)cfg.grid ? (items > 0 ? items : 1) : 2 * (int64_t)cfg.grid);
+        k_post<NT><<<g_post, NT, 0, stream>>>(d_hdr, ws);
+    }
     mark();
     const hipError_t le = hipGetLastError();
     return le != hipSuccess ? le : e;

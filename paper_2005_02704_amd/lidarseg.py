@@ -25,13 +25,15 @@ LIDAR_LAUNCH_PLAIN = 0
 LIDAR_LAUNCH_BATCHED = 1
 LIDAR_LAUNCH_GRAPH = 2
 LAUNCH = {"plain": LIDAR_LAUNCH_PLAIN, "batched": LIDAR_LAUNCH_BATCHED, "graph": LIDAR_LAUNCH_GRAPH}
+LIDAR_PRED_COMPONENTS = 0
+LIDAR_PRED_COSINE = 1
 
 # every symbol include/lidarseg.h declares
 EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lidar_last_error",
            "lidar_query_sizes", "lidar_mesh_segment", "lidar_ctx_set_tuning", "lidar_ctx_set_profiling",
            "lidar_ctx_stage_times")
-LIDAR_N_STAGES = 9
-STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label")
+LIDAR_N_STAGES = 10
+STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post")
 
 
 class LidarError(RuntimeError):
@@ -52,13 +54,15 @@ class lidar_frame_t(ctypes.Structure):
 
 
 class lidar_params_t(ctypes.Structure):
-    _fields_ = [("r_min", ctypes.c_double), ("r_max", ctypes.c_double), ("thr", ctypes.c_double * 3)]
+    _fields_ = [("r_min", ctypes.c_double), ("r_max", ctypes.c_double), ("thr", ctypes.c_double * 3),
+                ("predicate", ctypes.c_int32), ("min_segment", ctypes.c_int32), ("cos_min", ctypes.c_double)]
 
 
 class lidar_result_t(ctypes.Structure):
     _fields_ = [("vertices", ctypes.c_void_p), ("normals", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("triangles", ctypes.c_void_p),
-                ("vertex_point", ctypes.c_void_p), ("counts", ctypes.c_void_p)]
+                ("vertex_point", ctypes.c_void_p), ("counts", ctypes.c_void_p),
+                ("point_labels", ctypes.c_void_p)]
 
 
 _lib = None
@@ -140,7 +144,8 @@ def lidar_query_sizes(sensor: SensorGeometry):
 class Outputs:
     """Caller-owned device outputs of one frame (torch tensors at full capacity)."""
 
-    def __init__(self, sensor: SensorGeometry, device, with_vertex_point=True):
+    def __init__(self, sensor: SensorGeometry, device, with_vertex_point=True, n_points: int = 0):
+        """n_points > 0 also allocates point_labels (every input point's label)."""
         import torch
         V, T = lidar_query_sizes(sensor)
         self.vertices = torch.empty((max(V, 1), 3), dtype=torch.float32, device=device)
@@ -149,12 +154,14 @@ class Outputs:
         self.triangles = torch.empty((max(T, 1), 3), dtype=torch.int32, device=device)
         self.vertex_point = torch.empty(max(V, 1), dtype=torch.int32, device=device) if with_vertex_point else None
         self.counts = torch.zeros(3, dtype=torch.int64, device=device)
+        self.point_labels = torch.empty(n_points, dtype=torch.int32, device=device) if n_points > 0 else None
 
     def c_struct(self) -> lidar_result_t:
         return lidar_result_t(self.vertices.data_ptr(), self.normals.data_ptr(), self.labels.data_ptr(),
                               self.triangles.data_ptr(),
                               self.vertex_point.data_ptr() if self.vertex_point is not None else None,
-                              self.counts.data_ptr())
+                              self.counts.data_ptr(),
+                              self.point_labels.data_ptr() if self.point_labels is not None else None)
 
     def trimmed(self):
         """Views cut to the counts (synchronises with the device to read them)."""
@@ -164,7 +171,7 @@ class Outputs:
         return dict(vertices=self.vertices[:V], normals=self.normals[:V], labels=self.labels[:V],
                     triangles=self.triangles[:T],
                     vertex_point=self.vertex_point[:V] if self.vertex_point is not None else None,
-                    counts=(V, T, K))
+                    point_labels=self.point_labels, counts=(V, T, K))
 
 
 class LidarContext:
@@ -234,12 +241,14 @@ class LidarContext:
         self._check(rc)
 
 
-def make_params(r_min=1.0, r_max=60.0, thr=(0.2, 0.2, 0.2)) -> lidar_params_t:
-    return lidar_params_t(float(r_min), float(r_max), (ctypes.c_double * 3)(*[float(t) for t in thr]))
+def make_params(r_min=1.0, r_max=60.0, thr=(0.2, 0.2, 0.2), predicate=LIDAR_PRED_COMPONENTS, cos_min=0.0,
+                min_segment=0) -> lidar_params_t:
+    return lidar_params_t(float(r_min), float(r_max), (ctypes.c_double * 3)(*[float(t) for t in thr]),
+                          int(predicate), int(min_segment), float(cos_min))
 
 
 def lidar_mesh_segment(ctx: LidarContext, inputs, params: lidar_params_t | None = None,
-                       launch: str = "batched", stream=None, with_vertex_point=True):
+                       launch: str = "batched", stream=None, with_vertex_point=True, point_labels=False):
     """Convenience: inputs = [(xyz cuda float32 [N,3], SensorGeometry, normals_in or None)].
 
     Allocates outputs, enqueues the call and returns the Outputs objects (call
@@ -247,7 +256,7 @@ def lidar_mesh_segment(ctx: LidarContext, inputs, params: lidar_params_t | None 
     import torch
     params = params or make_params()
     dev = torch.device("cuda", ctx.device)
-    outs = [Outputs(s, dev, with_vertex_point) for (_x, s, _n) in inputs]
+    outs = [Outputs(s, dev, with_vertex_point, int(x.shape[0]) if point_labels else 0) for (x, s, _n) in inputs]
     prep = ctx.prepare(inputs, params, outs)
     ctx.lidar_mesh_segment(prep, stream=stream, launch=launch)
     return outs

@@ -15,7 +15,8 @@ def geometry(sensor, s=1, wrap=1):
     return lp.SensorGeometry(sensor.elevations(), sensor.n_azimuth, s, wrap, sensor.az0)
 
 
-def run_gpu(ctx, items, launch="plain", r_min=1.0, r_max=60.0, thr=THR):
+def run_gpu(ctx, items, launch="plain", r_min=1.0, r_max=60.0, thr=THR, predicate=0, cos_min=0.0, min_segment=0,
+            point_labels=False):
     """items: list of (xyz float32 [N,3] numpy, synth.Sensor, s, wrap, normals_in or None)."""
     import torch
     import paper_2005_02704_amd as lp
@@ -24,20 +25,22 @@ def run_gpu(ctx, items, launch="plain", r_min=1.0, r_max=60.0, thr=THR):
         x = torch.from_numpy(np.ascontiguousarray(xyz, np.float32)).cuda()
         n = torch.from_numpy(np.ascontiguousarray(nin, np.float32)).cuda() if nin is not None else None
         inputs.append((x, geometry(sen, s, wrap), n))
-    outs = lp.lidar_mesh_segment(ctx, inputs, lp.make_params(r_min, r_max, thr), launch=launch)
+    params = lp.make_params(r_min, r_max, thr, predicate, cos_min, min_segment)
+    outs = lp.lidar_mesh_segment(ctx, inputs, params, launch=launch, point_labels=point_labels)
     torch.cuda.synchronize()
     res = []
     for o in outs:
         t = o.trimmed()
         res.append(dict(vertices=t["vertices"].cpu().numpy(), normals=t["normals"].cpu().numpy(),
                         labels=t["labels"].cpu().numpy(), triangles=t["triangles"].cpu().numpy(),
-                        vertex_point=t["vertex_point"].cpu().numpy(), counts=t["counts"]))
+                        vertex_point=t["vertex_point"].cpu().numpy(), counts=t["counts"],
+                        point_labels=t["point_labels"].cpu().numpy() if t["point_labels"] is not None else None))
     return res
 
 
-def run_oracle(xyz, sen, s=1, wrap=1, r_min=1.0, r_max=60.0, thr=THR):
+def run_oracle(xyz, sen, s=1, wrap=1, r_min=1.0, r_max=60.0, thr=THR, **kw):
     return oracle.mesh_segment(xyz, sen.n_rings, sen.n_azimuth, s, sen.elevations(), az0=sen.az0,
-                               r_min=r_min, r_max=r_max, thr=thr, wrap=wrap)
+                               r_min=r_min, r_max=r_max, thr=thr, wrap=wrap, **kw)
 
 
 def normal_angles(a, b):
@@ -118,5 +121,43 @@ def margin_clear(xyz, sen, s=1, wrap=1, r_min=1.0, r_max=60.0, thr=THR, margin=M
         drop = cp[bad]
         keep = np.ones(xyz.shape[0], bool)
         keep[drop] = False
+        xyz = xyz[keep]
+    raise RuntimeError("margin clearing did not converge")
+
+
+def margin_clear_cos(xyz, sen, cos_min, s=1, wrap=1, r_min=1.0, r_max=60.0, margin=MARGIN, rounds=12):
+    """As margin_clear, for the cosine test: drop points until no mesh join between
+    two vertices with normals has a dot product within `margin` of cos_min."""
+    xyz = np.ascontiguousarray(xyz, np.float32)
+    H = sen.n_rings
+    Wp = sen.n_azimuth // s
+    for _ in range(rounds):
+        cp = oracle.bin_points(xyz, H, sen.n_azimuth, s, sen.elevations(), sen.az0, r_min, r_max)
+        valid = (cp >= 0).astype(np.uint8)
+        cell_xyz = np.zeros((H * Wp, 3), np.float32)
+        cell_xyz[valid == 1] = xyz[cp[valid == 1]]
+        n64, hasn = oracle.normals(H, Wp, wrap, cell_xyz, valid)
+        n32 = n64.astype(np.float32).astype(np.float64)
+        bad = np.zeros(H * Wp, bool)
+        ii = np.tile(np.arange(H), Wp)
+        kk = np.repeat(np.arange(Wp), H)
+        c = np.arange(H * Wp)
+        for di, dk in ((1, 0), (1, 1), (0, 1)):
+            i2 = ii + di
+            k2 = kk + dk
+            ok = i2 < H
+            if wrap:
+                k2 = k2 % Wp
+            else:
+                ok &= k2 < Wp
+            q = np.where(ok, k2 * H + np.minimum(i2, H - 1), 0)
+            both = ok & (hasn[c] == 1) & (hasn[q] == 1)
+            dot = np.einsum("ij,ij->i", n32[c], n32[q])
+            hit = both & (np.abs(dot - cos_min) < margin)
+            bad[c[hit]] = True
+        if not bad.any():
+            return xyz
+        keep = np.ones(xyz.shape[0], bool)
+        keep[cp[bad]] = False
         xyz = xyz[keep]
     raise RuntimeError("margin clearing did not converge")

@@ -1,0 +1,39 @@
+"""The launch-shape autotuner's host side: batch classes, the committed table,
+and that every shape it may choose is one the library accepts."""
+import numpy as np
+
+import paper_2005_02704_amd as lp
+from paper_2005_02704_amd import autotune
+
+
+def _geo(h, w, s=1):
+    return lp.SensorGeometry(np.linspace(0.2, -0.3, h), w, s)
+
+
+def test_batch_class_buckets():
+    assert autotune.batch_class([_geo(16, 1800)]) == "H16-W2048-F1"
+    assert autotune.batch_class([_geo(64, 2048, 2)]) == "H64-W1024-F1"
+    assert autotune.batch_class([_geo(16, 1024), _geo(128, 4096)] * 10) == "H128-W4096-F64"
+    assert autotune.batch_class([_geo(100, 9000)] * 300) == "H128-W16384-F512"
+
+
+def test_lookup_falls_back_to_the_default():
+    assert autotune.lookup([_geo(7, 333)], table={}) == autotune.DEFAULT
+
+
+def test_committed_table_holds_supported_shapes():
+    table = autotune.load_table()
+    assert table, "tune_table.json is missing"
+    shapes = {(c, t) for c, t in autotune.TILE_SHAPES}
+    for key, entry in table.items():
+        assert (entry["tile_cells"], entry["tile_threads"]) in shapes, key
+        assert entry["grid"] in autotune.GRIDS
+        assert entry["ms"] <= entry["default_ms"] + 1e-9
+    # the benchmark batch has an entry
+    assert "H128-W4096-F64" in table
+
+
+def test_candidates_cover_every_shape_and_grid():
+    c = autotune.candidates()
+    assert len(c) == len(autotune.TILE_SHAPES) * len(autotune.GRIDS)
+    assert len({tuple(sorted(x.items())) for x in c}) == len(c)
