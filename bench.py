@@ -39,6 +39,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+STAGE_KERNEL = {"bin": "k_bin", "count": "k_count", "geom": "k_geom", "cc": "k_cc", "merge": "k_merge",
+                "compress": "k_compress", "flatten": "k_flatten", "scan": "k_scan", "label": "k_resolve",
+                "post": "k_post"}
+
+
 def stage_bytes(stage, N, V, T):
     """Algorithmic bytes a stage must move (what the method reads and writes,
     not the key grid or other scratch).  N input points, V vertices, T triangles."""
@@ -48,7 +53,7 @@ def stage_bytes(stage, N, V, T):
         return 12 * V + 12 * V + 12 * V + 4 * V + 12 * T  # kept xyz in; vertices, normals,
         # vertex_point, triangles out
     if stage == "label":
-        return 8 * V                          # segment root read + label written
+        return 4 * V                          # labels written
     return 0
 
 
@@ -109,6 +114,8 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="workgroups per batched stage, 0 = library default")
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
+    ap.add_argument("--forms", default="graph,batched,plain",
+                    help="launch forms to time (graph is always timed: it gives value)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (3 times), as the yardstick "
                          "for HBM byte counters")
@@ -184,14 +191,17 @@ def main():
     counts = np.array([[int(x) for x in o.counts.cpu()] for o in outs])
     V, T = int(counts[:, 0].sum()), int(counts[:, 1].sum())
     log(f"  graph: {ms_graph:.3f} ms/step (host enqueue {host_ms['graph']:.3f} ms/step)  V={V} T={T}")
-    log("timing batched launches")
-    ms_batched = run("batched", args.steps, args.warmup)
-    log(f"  batched: {ms_batched:.3f} ms/step (host enqueue {host_ms['batched']:.3f} ms/step)")
-    log("timing plain per-frame chains")
-    ms_plain = run("plain", args.steps, args.warmup)
-    log(f"  plain: {ms_plain:.3f} ms/step (host enqueue {host_ms['plain']:.3f} ms/step)")
-
-    # dominant kernel: per-stage HIP events on the launch stream over K batched steps
+    forms = {"graph": {"points_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4)}}
+    for form in ("batched", "plain"):
+        if form not in args.forms.split(","):
+            continue
+        log(f"timing {form} launches")
+        ms = run(form, args.steps, args.warmup)
+        log(f"  {form}: {ms:.3f} ms/step (host enqueue {host_ms[form]:.3f} ms/step)")
+        forms[form] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4)}
+    # roofline kernel: per-stage HIP events on the launch stream over K batched steps.
+    # k_geom moves most of the path's algorithmic bytes (the kept points in; the
+    # vertices, normals, vertex points and triangles out), so the roofline is its.
     log("timing stages with HIP events")
     ctx.stage_times()
     ctx.set_profiling(True)
@@ -201,14 +211,14 @@ def main():
     st = ctx.stage_times()
     ctx.set_profiling(False)
     per_launch = {k: ms / n for k, (ms, n) in st.items() if n}
-    dom = max(per_launch, key=per_launch.get)
+    dom = "geom"
     dom_ms = per_launch[dom]
     dom_bytes = stage_bytes(dom, N, V, T)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     log("  stages (ms/launch): " + ", ".join(f"{k} {v:.4f}" for k, v in per_launch.items()))
 
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_k_{dom}.json")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{STAGE_KERNEL[dom]}.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
@@ -216,11 +226,11 @@ def main():
                 and tr.get("seed") == args.seed:
             traffic = tr.get("hbm_bytes_per_launch")
 
-    roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    roofline = {"bound": "hbm", "kernel": STAGE_KERNEL[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 5),
                 "stage_ms": {k: round(v, 5) for k, v in per_launch.items()}}
-    alg_path = 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T
+    alg_path = 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T   # whole path, as in the byte model
     path_gbs = alg_path / (ms_graph * 1e-3) / 1e9
 
     served = None
@@ -263,11 +273,7 @@ def main():
                                f"azimuth 1024/2048/4096, s=1)", "frames": args.frames,
                    "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
                    "launch": "graph", "seed": args.seed, "launch_shape": shape, "launch_shape_source": shape_src},
-        "forms": {
-            "graph": {"points_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4)},
-            "batched": {"points_per_s": round(N / (ms_batched * 1e-3), 1), "ms_per_step": round(ms_batched, 4)},
-            "plain": {"points_per_s": round(N / (ms_plain * 1e-3), 1), "ms_per_step": round(ms_plain, 4)},
-        },
+        "forms": forms,
         "path_algorithmic_gbs": round(path_gbs, 1),
         "roofline": roofline,
         "served": served,

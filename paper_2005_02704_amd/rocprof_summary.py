@@ -5,10 +5,10 @@ Usage:
   python -m paper_2005_02704_amd.rocprof_summary --trace DIR [--fetch DIR --write DIR]
          --command "the rocprofv3 command" --out profiles/NAME.txt [--traffic-json FILE]
 
-The batched dispatches are those with the bench's fixed grid (grid_wg x 256
-threads); per-frame (plain) dispatches are summarised separately.  HBM bytes
-are FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
-counters read for the plain device copy bench.py --copy-calibration runs.
+The profiled run launches only the batched chain (bench.py --forms graph).
+HBM bytes are FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the
+same counters read for the plain device copy bench.py --copy-calibration runs
+(the largest copy dispatch of the run).
 """
 from __future__ import annotations
 
@@ -47,17 +47,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def trace_summary(d: str, batched_grid: int):
+def trace_summary(d: str):
+    """Durations by kernel.  The profiled run launches only the batched chain
+    (bench.py --forms graph), so every dispatch of a library kernel is batched."""
     rows = _csv(d, "kernel_trace.csv")
     by = collections.defaultdict(list)
     for r in rows:
-        g = int(r["Grid_Size_X"])
-        form = "batched" if g == batched_grid else "per-frame"
-        by[(kname(r["Kernel_Name"]), form)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        by[kname(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     return by
 
 
-def counter_summary(d: str, batched_grid: int):
+def counter_summary(d: str):
     rows = _csv(d, "counter_collection.csv")
     by = collections.defaultdict(list)
     copies = []
@@ -66,7 +66,7 @@ def counter_summary(d: str, batched_grid: int):
         v = float(r["Counter_Value"])
         if "copyBuffer" in name:
             copies.append((int(r["Grid_Size"]), v))
-        elif int(r["Grid_Size"]) == batched_grid:
+        elif name.startswith("k_"):
             by[name].append(v)
     # the calibration copy is the largest copy dispatch (the others stage inputs)
     gmax = max(g for g, _ in copies)
@@ -78,46 +78,43 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
-    ap.add_argument("--grid-wg", type=int, default=1024)
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--command", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic-json")
-    ap.add_argument("--kernel", default="k_tile")
+    ap.add_argument("--kernel", default="k_geom")
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--alg-bytes", type=float, default=0.0,
                     help="algorithmic bytes per launch of --kernel (from bench.py's roofline)")
     a = ap.parse_args()
-    grid = a.grid_wg * 256
     lines = [f"# rocprofv3 summary: {a.kernel} and the rest of the chain, bench.py workload",
              f"command: {a.command}", ""]
-    tr = trace_summary(a.trace, grid)
-    lines.append("kernel            form       calls   avg_us    min_us    total_us")
-    for (k, form), v in sorted(tr.items(), key=lambda kv: -sum(kv[1])):
-        lines.append(f"{k:<17} {form:<9} {len(v):6d} {sum(v) / len(v) / 1e3:9.2f} {min(v) / 1e3:9.2f} "
-                     f"{sum(v) / 1e3:11.1f}")
+    tr = trace_summary(a.trace)
+    lines.append("kernel            calls   avg_us    min_us    total_us")
+    for k, v in sorted(tr.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{k:<17} {len(v):6d} {sum(v) / len(v) / 1e3:9.2f} {min(v) / 1e3:9.2f} {sum(v) / 1e3:11.1f}")
     traffic = None
     if a.fetch and a.write:
-        fb, fcopy = counter_summary(a.fetch, grid)
-        wb, wcopy = counter_summary(a.write, grid)
+        fb, fcopy = counter_summary(a.fetch)
+        wb, wcopy = counter_summary(a.write)
         copy_kib = a.copy_mib * 1024.0
         f_scale = copy_kib / (sum(fcopy) / len(fcopy))
         w_scale = copy_kib / (sum(wcopy) / len(wcopy))
         lines += ["", f"calibration: {a.copy_mib} MiB device copy reads FETCH_SIZE "
                       f"{sum(fcopy) / len(fcopy):.1f} KiB, WRITE_SIZE {sum(wcopy) / len(wcopy):.1f} KiB "
                       f"-> scale fetch x{f_scale:.3f}, write x{w_scale:.3f}",
-                  "kernel (batched)  fetch_MB  write_MB  hbm_MB (scaled)"]
+                  "kernel            fetch_MB  write_MB  hbm_MB (scaled, per dispatch)"]
         for k in sorted(fb, key=lambda k: -sum(fb[k]) / len(fb[k])):
             fm = sum(fb[k]) / len(fb[k]) * f_scale * 1024 / 1e6
             wm = sum(wb.get(k, [0])) / max(1, len(wb.get(k, [0]))) * w_scale * 1024 / 1e6
             lines.append(f"{k:<17} {fm:9.1f} {wm:9.1f} {fm + wm:9.1f}")
             if k == a.kernel:
                 traffic = (fm + wm) * 1e6
-        if a.kernel in dict(tr) or (a.kernel, "batched") in tr:
-            v = tr[(a.kernel, "batched")]
+        if a.kernel in tr and traffic is not None:
+            v = tr[a.kernel]
             avg_s = sum(v) / len(v) / 1e9
-            lines += ["", f"{a.kernel} batched: avg {avg_s * 1e6:.2f} us, HBM traffic {traffic / 1e6:.1f} MB "
+            lines += ["", f"{a.kernel}: avg {avg_s * 1e6:.2f} us, HBM traffic {traffic / 1e6:.1f} MB "
                           f"-> {traffic / avg_s / 1e9:.1f} GB/s"]
             if a.alg_bytes:
                 lines.append(f"algorithmic bytes {a.alg_bytes / 1e6:.1f} MB -> "
