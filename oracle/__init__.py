@@ -61,6 +61,8 @@ def lib():
         L.oracle_point_cells.restype = None
         L.oracle_backfill.argtypes = [i64, P, P, i32, i32, i32, i32, P, P]
         L.oracle_backfill.restype = None
+        L.oracle_edge_scores.argtypes = [i32, i32, i32, P, P, i32, P]
+        L.oracle_edge_scores.restype = None
         L.oracle_mesh_segment_ex.argtypes = [P, i64, i32, i32, i32, i32, P, f64, f64, f64, i32, P, f64, i32,
                                              P, P, P, P, P, P, P, P]
         L.oracle_mesh_segment_ex.restype = ctypes.c_int
@@ -157,6 +159,39 @@ def backfill(ring, firing, H, W, s, wrap, cell_label):
     out = np.empty(ring.shape[0], np.int32)
     lib().oracle_backfill(ring.shape[0], _p(ring), _p(firing), H, W, s, wrap, _p(cell_label), _p(out))
     return out
+
+
+def edge_scores(H, Wp, wrap, cell_label, cell_truth, radius=1):
+    """Step 7: (segment edges, truth edges, found, recalled) of a labelled lattice.
+    cell_label: [H * Wp] label of each cell's vertex, -1 for an empty cell;
+    cell_truth: [H * Wp] ground-truth surface id of each cell's vertex."""
+    cell_label = _c(cell_label, np.int32)
+    cell_truth = _c(cell_truth, np.int32)
+    out = np.zeros(4, np.int64)
+    lib().oracle_edge_scores(H, Wp, wrap, _p(cell_label), _p(cell_truth), int(radius), _p(out))
+    return tuple(int(x) for x in out)
+
+
+def precision_recall_f1(counts):
+    """Precision, recall and F1 from edge counts; a side with no edges scores 1
+    when the other has none either, else 0."""
+    n_seg, n_tru, found, recalled = counts
+    p = found / n_seg if n_seg else (1.0 if n_tru == 0 else 0.0)
+    r = recalled / n_tru if n_tru else (1.0 if n_seg == 0 else 0.0)
+    f = 2 * p * r / (p + r) if p + r > 0 else 0.0
+    return p, r, f
+
+
+def frame_edge_scores(xyz, truth, H, W, s, elev, labels, *, az0=0.0, r_min=1.0, r_max=60.0, wrap=1, radius=1):
+    """Edge counts of one sweep's vertex labels (vertex order) against the
+    per-point truth ids, through the sweep's own binning."""
+    cp = bin_points(xyz, H, W, s, elev, az0, r_min, r_max)
+    used = cp >= 0
+    cell_label = np.full(cp.shape[0], -1, np.int32)
+    cell_truth = np.full(cp.shape[0], -1, np.int32)
+    cell_label[used] = np.asarray(labels, np.int32)
+    cell_truth[used] = np.asarray(truth, np.int32)[cp[used]]
+    return edge_scores(H, W // s, wrap, cell_label, cell_truth, radius)
 
 
 @dataclass

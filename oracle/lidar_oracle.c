@@ -12,6 +12,7 @@
  *   5. Algorithm 1: depth-first label propagation                 -- Section 2, Algorithm 1
  *   6. labels for the points the sub-sampling skipped, and removal of
  *      segments with too few points (optional)                    -- Section 2, Segmentation
+ *   7. edge scores of the segments against ground-truth surfaces  -- Section 3 (evaluation)
  *
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg load
  * this library.  It shares no source, header or table with the GPU library.
@@ -41,7 +42,11 @@
  *     closed), the earlier firing on a tie; 0 if its ring has no vertex or the
  *     point was not used;
  *   - a segment has "too few points" when fewer than min_segment vertices carry
- *     its label; its vertices (and the points that took its label) get label 0.
+ *     its label; its vertices (and the points that took its label) get label 0;
+ *   - the evaluation's "edge points" are the vertices with a mesh join to a
+ *     vertex of another label (or, for the ground truth, of another surface);
+ *     "dilated" means grown by R lattice steps in ring and in column (Chebyshev
+ *     distance, columns around the cylinder when it is closed).
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -o liblidar_oracle.so lidar_oracle.c -lm
  */
@@ -471,4 +476,64 @@ int oracle_mesh_segment(const float* xyz, int64_t n, int32_t H, int32_t W, int32
     return oracle_mesh_segment_ex(xyz, n, H, W, s, wrap, elev, az0, r_min, r_max, 0, thr, 0.0, 0,
                                   vertices, normals, labels, triangles, vertex_point, counts, normals64,
                                   NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 7: edge scores (Section 3: the segments are compared with the ground
+ * truth through their edge points, each side dilated, and scored by
+ * precision, recall and F1).
+ * label[c] is the label of cell c's vertex (-1: empty cell), truth[c] its
+ * ground-truth surface id.  A vertex is a segment edge when one of its mesh
+ * joins (the six neighbours A..F) reaches a vertex of another label, a truth
+ * edge when one reaches a vertex of another truth id.  A segment edge is
+ * found when some truth edge lies within R rings and R columns of it; a truth
+ * edge is recalled when some segment edge does.
+ * out = {segment edges, truth edges, found, recalled}. */
+static int col_within(int32_t Wp, int32_t wrap, int32_t k, int32_t k2, int32_t R)
+{
+    int32_t d = k > k2 ? k - k2 : k2 - k;
+    if (wrap && Wp - d < d) d = Wp - d;
+    return d <= R;
+}
+
+void oracle_edge_scores(int32_t H, int32_t Wp, int32_t wrap, const int32_t* label, const int32_t* truth,
+                        int32_t R, int64_t* out)
+{
+    const int64_t cells = (int64_t)H * Wp;
+    uint8_t* seg_edge = calloc((size_t)(cells > 0 ? cells : 1), 1);
+    uint8_t* tru_edge = calloc((size_t)(cells > 0 ? cells : 1), 1);
+    out[0] = out[1] = out[2] = out[3] = 0;
+    for (int32_t k = 0; k < Wp; ++k)
+        for (int32_t i = 0; i < H; ++i) {
+            const int64_t c = (int64_t)k * H + i;
+            if (label[c] < 0) continue;
+            for (int t = 0; t < 6; ++t) {
+                const int64_t q = neighbour_cell(H, Wp, wrap, i, k, t);
+                if (q < 0 || label[q] < 0) continue;
+                if (label[q] != label[c]) seg_edge[c] = 1;
+                if (truth[q] != truth[c]) tru_edge[c] = 1;
+            }
+            out[0] += seg_edge[c];
+            out[1] += tru_edge[c];
+        }
+    /* every pair of edge cells within the window, by brute force */
+    for (int32_t k = 0; k < Wp; ++k)
+        for (int32_t i = 0; i < H; ++i) {
+            const int64_t c = (int64_t)k * H + i;
+            if (!seg_edge[c] && !tru_edge[c]) continue;
+            int found = 0, recalled = 0;
+            for (int32_t k2 = 0; k2 < Wp; ++k2) {
+                if (!col_within(Wp, wrap, k, k2, R)) continue;
+                for (int32_t i2 = i - R; i2 <= i + R; ++i2) {
+                    if (i2 < 0 || i2 >= H) continue;
+                    const int64_t q = (int64_t)k2 * H + i2;
+                    if (tru_edge[q]) found = 1;
+                    if (seg_edge[q]) recalled = 1;
+                }
+            }
+            if (seg_edge[c] && found) ++out[2];
+            if (tru_edge[c] && recalled) ++out[3];
+        }
+    free(seg_edge);
+    free(tru_edge);
 }
