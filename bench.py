@@ -41,7 +41,7 @@ def kernel_source_hash():
 
 STAGE_KERNEL = {"bin": "k_bin", "count": "k_count", "geom": "k_geom", "cc": "k_cc", "merge": "k_merge",
                 "compress": "k_compress", "flatten": "k_flatten", "scan": "k_scan", "label": "k_resolve",
-                "post": "k_post"}
+                "post": "k_post", "score": "k_score"}
 
 
 def stage_bytes(stage, N, V, T):
@@ -100,6 +100,53 @@ def served_run(args, lp, synth, torch):
             "capacity_mean_batch": round(stc["mean_batch"], 2)}
 
 
+def mean_scores(outs, lp):
+    prf = [lp.precision_recall_f1(tuple(int(x) for x in o.edge_counts.cpu())) for o in outs]
+    return {k: round(float(sum(v[j] for v in prf) / len(prf)), 4) for j, k in enumerate(("precision", "recall", "f1"))}
+
+
+def accuracy_run(args, lp, synth, torch, ctx, frames, geos, stream):
+    """Edge scores (segment edges against the generator's surface ids, each
+    dilated by one lattice step), averaged over frames: on the benchmark batch
+    (with the time of the scoring stage), and at the paper's own sweep shape
+    (32 rings x 1800 firings) for sampling intervals 5, 10 and 15."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2), score_radius=1)
+    inputs = [(torch.from_numpy(f.xyz).to(dev), g, None, torch.from_numpy(f.prim.astype(np.int32)).to(dev))
+              for f, g in zip(frames, geos)]
+    outs = [lp.Outputs(g, dev, scores=True) for g in geos]
+    prep = ctx.prepare(inputs, params, outs)
+    for _ in range(3):
+        ctx.lidar_mesh_segment(prep, stream, "batched")
+    torch.cuda.synchronize()
+    ctx.stage_times()
+    ctx.set_profiling(True)
+    for _ in range(10):
+        ctx.lidar_mesh_segment(prep, stream, "batched")
+    torch.cuda.synchronize()
+    st = ctx.stage_times()
+    ctx.set_profiling(False)
+    batch = {**mean_scores(outs, lp), "score_ms": round(st["score"][0] / max(st["score"][1], 1), 5)}
+    log(f"  batch edge scores {batch}")
+    w = synth.WORKLOADS["paper_32x1800"]
+    n_env = 8
+    envs = synth.workload_frames("paper_32x1800", n_env)
+    paper = {}
+    for s in w["s"]:
+        g = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, s, 1, f.sensor.az0) for f in envs]
+        inp = [(torch.from_numpy(f.xyz).to(dev), gg, None, torch.from_numpy(f.prim.astype(np.int32)).to(dev))
+               for f, gg in zip(envs, g)]
+        o = [lp.Outputs(gg, dev, scores=True) for gg in g]
+        ctx.lidar_mesh_segment(ctx.prepare(inp, params, o), stream, "batched")
+        torch.cuda.synchronize()
+        paper[str(s)] = mean_scores(o, lp)
+        log(f"  paper shape, interval {s}: {paper[str(s)]}")
+    return {"measure": "edge points (a mesh join to another label / another surface), dilated by 1 lattice step; "
+                       "precision, recall, F1 averaged over frames; truth = generator surface ids",
+            "batch": batch, "paper_shape_32x1800": paper, "paper_shape_environments": n_env}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +163,7 @@ def main():
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
     ap.add_argument("--forms", default="graph,batched,plain",
                     help="launch forms to time (graph is always timed: it gives value)")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the edge-score leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (3 times), as the yardstick "
                          "for HBM byte counters")
@@ -233,6 +281,11 @@ def main():
     alg_path = 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T   # whole path, as in the byte model
     path_gbs = alg_path / (ms_graph * 1e-3) / 1e9
 
+    accuracy = None
+    if not args.no_accuracy:
+        log("edge scores")
+        accuracy = accuracy_run(args, lp, synth, torch, ctx, frames, geos, stream)
+
     served = None
     if args.served_seconds > 0:
         served = served_run(args, lp, synth, torch)
@@ -277,6 +330,7 @@ def main():
         "path_algorithmic_gbs": round(path_gbs, 1),
         "roofline": roofline,
         "served": served,
+        "accuracy": accuracy,
         "cpu_baseline": cpu,
     }
     ctx.close()

@@ -77,6 +77,9 @@ typedef struct {
                                       stage is skipped and these per-vertex normals
                                       (zero vector = no normal) are labelled instead;
                                       V must be this frame's vertex count. */
+    const int32_t* truth_ids;      /* device [n_points] or NULL: ground-truth surface id
+                                      of every input point, read only for the edge
+                                      scores (lidar_result_t.edge_counts) */
 } lidar_frame_t;
 
 /* Similarity tests of lidar_params_t.predicate. */
@@ -97,7 +100,11 @@ typedef struct {
     int32_t min_segment;  /* >= 2: labels carried by fewer vertices become 0 (the count
                              K is unchanged); 0 or 1: keep every segment */
     double cos_min;       /* LIDAR_PRED_COSINE threshold, in [-1, 1) */
+    int32_t score_radius; /* edge scores: dilation radius R in lattice steps,
+                             0..LIDAR_MAX_SCORE_RADIUS */
 } lidar_params_t;
+
+#define LIDAR_MAX_SCORE_RADIUS 8
 
 /* Caller-owned outputs of one frame, sized by lidar_query_sizes().  Written
  * compactly from index 0; counts tells how many entries are valid. */
@@ -116,6 +123,17 @@ typedef struct {
                                cylinder when it is closed -- the earlier firing on a
                                tie); 0 for a point that is not used or whose ring has
                                no vertex */
+    int64_t* edge_counts;   /* device [4] or NULL: edge scores of the labels against
+                               the frame's truth_ids (Section 3 scores segmentations
+                               by their dilated edge points: precision, recall, F1).
+                               A vertex is a segment edge when a mesh join reaches a
+                               vertex of another label (after segment removal), a
+                               truth edge when one reaches a vertex of another truth
+                               id.  Written: {segment edges, truth edges, segment
+                               edges with a truth edge within R rings and R columns
+                               (around the cylinder when closed), truth edges with a
+                               segment edge that near}.  precision = [2] / [0],
+                               recall = [3] / [1].  Needs truth_ids. */
 } lidar_result_t;
 
 /* Create a context on HIP device `device`.  The context owns its device
@@ -154,8 +172,9 @@ int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_c
  * segments), merge (segments across tiles), compress (pointer jumping on the
  * merged segments), flatten (segment roots), scan (rank bases of the roots),
  * label, post (segment removal and point labels; zero time when neither is
- * asked for).  Enabling costs one event per kernel. */
-#define LIDAR_N_STAGES 10
+ * asked for), score (edge scores; zero time unless asked for).  Enabling costs
+ * one event per kernel. */
+#define LIDAR_N_STAGES 11
 int lidar_ctx_set_profiling(lidar_ctx* ctx, int32_t enable);
 /* Waits for the profiled calls, then writes the summed milliseconds and the
  * number of timed launches of each stage (arrays of LIDAR_N_STAGES; launches

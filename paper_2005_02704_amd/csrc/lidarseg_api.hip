@@ -43,9 +43,10 @@ struct lidar_ctx {
     int64_t border_cap = 0;
     int32_t* pcell = nullptr;     // per input point record (point labels)
     int64_t pcell_cap = 0;
-    int32_t* cvid = nullptr;      // per cell vertex id (point labels)
+    int32_t* cvid = nullptr;      // per cell vertex id (point labels, edge scores)
     int32_t* segsize = nullptr;   // per label size (segment removal)
-    int64_t aux_cells_cap = 0;    // capacity of cvid and segsize
+    int32_t* vtruth = nullptr;    // per vertex truth id (edge scores)
+    int64_t aux_cells_cap = 0;    // capacity of cvid, segsize and vtruth
     char* d_table = nullptr;      // descriptor tables + elevations
     char* h_table[2] = {nullptr, nullptr};  // pinned staging of d_table, used alternately
     size_t table_cap = 0;
@@ -65,6 +66,7 @@ struct lidar_ctx {
     int graph_tile_threads = 0;
     int graph_grid = 0;
     bool graph_post = false;
+    bool graph_score = false;
 
     // tuning
     int grid_wg = 0;      // 0 = automatic
@@ -114,6 +116,7 @@ struct lidar_ctx {
         ws.pcell = pcell;
         ws.cvid = cvid;
         ws.segsize = segsize;
+        ws.vtruth = vtruth;
         ws.elev = reinterpret_cast<const double*>(d_table);
         return ws;
     }
@@ -229,6 +232,7 @@ void lidar_ctx_destroy(lidar_ctx* c) {
     if (c->pcell) (void)hipFree(c->pcell);
     if (c->cvid) (void)hipFree(c->cvid);
     if (c->segsize) (void)hipFree(c->segsize);
+    if (c->vtruth) (void)hipFree(c->vtruth);
     if (c->d_table) (void)hipFree(c->d_table);
     for (int b = 0; b < 2; ++b) {
         if (c->h_table[b]) (void)hipHostFree(c->h_table[b]);
@@ -309,7 +313,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     std::vector<FramePlan> plan(n_frames);
     int64_t cells = 0, border_slots = 0, elev_total = 0;
     int64_t tiles = 0, pblk = 0, vitems = 0, labelled_points = 0, max_points_f = 0;
-    bool any_point_labels = false;
+    bool any_point_labels = false, any_score = false;
     int64_t max_cells = 0, max_tiles_f = 0, max_pblk_f = 0, max_vitem_f = 0, max_border_f = 0;
     for (int f = 0; f < n_frames; ++f) {
         const lidar_frame_t& fr = frames[f];
@@ -328,6 +332,13 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         }
         if (fr.n_points > 0 && !fr.xyz)
             return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": xyz is NULL");
+        if (results[f].edge_counts) {
+            if (fr.n_points > 0 && !fr.truth_ids)
+                return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": edge scores need truth_ids");
+            if (params->score_radius < 0 || params->score_radius > LIDAR_MAX_SCORE_RADIUS)
+                return c->fail(LIDAR_EINVAL, "score_radius must lie in [0, LIDAR_MAX_SCORE_RADIUS]");
+            any_score = true;
+        }
         const lidar_result_t& r = results[f];
         if (!r.vertices || !r.normals || !r.labels || !r.triangles || !r.counts)
             return c->fail(LIDAR_EINVAL, "result " + std::to_string(f) + ": a required output is NULL");
@@ -387,7 +398,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     const bool grow = cells > c->keys_cap || tiles > c->tiles_cap || vitems > c->vitems_cap ||
                       border_slots > c->border_cap || table_bytes > c->table_cap ||
                       (any_point_labels && labelled_points > c->pcell_cap) ||
-                      ((any_point_labels || prune) && cells > c->aux_cells_cap);
+                      ((any_point_labels || prune || any_score) && cells > c->aux_cells_cap);
     if (grow) {
         int rc = c->wait_idle();
         if (rc) return rc;
@@ -448,14 +459,17 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             }
             c->pcell_cap = cap;
         }
-        if ((any_point_labels || prune) && cells > c->aux_cells_cap) {
+        if ((any_point_labels || prune || any_score) && cells > c->aux_cells_cap) {
             if (c->cvid) (void)hipFree(c->cvid);
             if (c->segsize) (void)hipFree(c->segsize);
+            if (c->vtruth) (void)hipFree(c->vtruth);
             c->cvid = nullptr;
             c->segsize = nullptr;
+            c->vtruth = nullptr;
             const int64_t cap = std::max<int64_t>(cells, c->aux_cells_cap * 3 / 2);
             if (hipMalloc(&c->cvid, sizeof(int32_t) * cap) != hipSuccess ||
-                hipMalloc(&c->segsize, sizeof(int32_t) * cap) != hipSuccess) {
+                hipMalloc(&c->segsize, sizeof(int32_t) * cap) != hipSuccess ||
+                hipMalloc(&c->vtruth, sizeof(int32_t) * cap) != hipSuccess) {
                 c->aux_cells_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate per-cell label arrays");
             }
@@ -515,6 +529,9 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         d.border_off = border_off;
         d.pt_off = pt_off;
         d.point_labels = r.point_labels;
+        d.truth = r.edge_counts ? fr.truth_ids : nullptr;
+        d.scores = r.edge_counts;
+        d.score_r = params->score_radius;
         d.pred = params->predicate;
         d.min_seg = params->min_segment;
         d.cos_min = params->cos_min;
@@ -564,6 +581,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.max_border = (int)plan[f].border_slots;
             cfg.max_frames = 1;
             cfg.post = prune || results[f].point_labels;
+            cfg.score = results[f].edge_counts != nullptr;
             cfg.grid = std::max(std::max(plan[f].n_tiles, plan[f].n_pblk), plan[f].n_vitem);
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table + offs[f]), ws, cfg, stream, ev);
@@ -605,6 +623,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.max_border = (int)border_slots;
             cfg.max_frames = n_frames;
             cfg.post = post;
+            cfg.score = any_score;
             cfg.grid = auto_grid;
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
@@ -613,23 +632,24 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             // The captured chain uses fixed grid-stride grids and reads the batch
             // from the device table, so it serves every batch that fits the workspace.
             if (!c->graph_valid || c->graph_table_bytes != c->table_cap || c->graph_tile_cells != c->tile_cells ||
-                c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid || c->graph_post != post) {
+                c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid || c->graph_post != post ||
+                c->graph_score != any_score) {
                 c->drop_graph();
                 hipStream_t cap_stream;
                 e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
                 if (e != hipSuccess) return c->hip_fail(e, "hipStreamCreate");
                 e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-                if (e != hipSuccess) { hipStreamDestroy(cap_stream); return c->hip_fail(e, "hipStreamBeginCapture"); }
+                if (e != hipSuccess) { (void)hipStreamDestroy(cap_stream); return c->hip_fail(e, "hipStreamBeginCapture"); }
                 LaunchCfg cfg;
                 cfg.tile_cells = c->tile_cells;
                 cfg.tile_threads = c->tile_threads;
-            cfg.tile_threads = c->tile_threads;
                 cfg.max_tiles = (int)std::min<int64_t>(c->tiles_cap, INT32_MAX);
                 cfg.max_pblk = INT32_MAX;
                 cfg.max_vitems = (int)std::min<int64_t>(c->vitems_cap, INT32_MAX);
                 cfg.max_border = (int)std::min<int64_t>(c->border_cap, INT32_MAX);
                 cfg.max_frames = INT32_MAX;
                 cfg.post = post;
+                cfg.score = any_score;
                 cfg.grid = auto_grid;
                 hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
                 e = hipStreamEndCapture(cap_stream, &c->graph);
@@ -646,6 +666,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 c->graph_tile_threads = c->tile_threads;
                 c->graph_grid = auto_grid;
                 c->graph_post = post;
+                c->graph_score = any_score;
             }
             e = hipGraphLaunch(c->graph_exec[c->graph_next], stream);
             c->graph_next ^= 1;

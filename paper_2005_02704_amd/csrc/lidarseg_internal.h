@@ -15,6 +15,7 @@ constexpr int64_t MAX_CELLS = 1ll << 29;     // per frame; keeps every count bel
 constexpr int64_t MAX_BATCH_CELLS = (1ll << 31) - VITEM;  // forest positions are int32
 constexpr int MAX_TILE_CELLS = 2048;
 constexpr int OCC_WORDS = MAX_TILE_CELLS / 64;        // occupancy words per tile
+constexpr int MAX_SCORE_RADIUS = 8;          // dilation radius of the edge scores
 
 // One frame of a batch, as the kernels see it.  Lives in device memory right
 // after a BatchHeader; all offsets index the context's workspace arrays.
@@ -28,6 +29,8 @@ struct FrameDesc {
     int32_t* vpoint;          // may be null
     int64_t* counts;
     int32_t* point_labels;    // may be null: every input point's label
+    const int32_t* truth;     // may be null: ground-truth surface id per input point
+    int64_t* scores;          // may be null: the frame's edge counts (needs truth)
     int64_t n_points;
     int64_t cell_off;         // first cell of this frame in the key grid and the forest
     int64_t border_off;       // first border slot (int2) of this frame: 2H slots per tile
@@ -39,7 +42,7 @@ struct FrameDesc {
     int32_t elev_off;
     int32_t pred;             // similarity test: 0 components (Algorithm 1), 1 cosine
     int32_t min_seg;          // >= 2: segments with fewer vertices get label 0
-    int32_t pad0;
+    int32_t score_r;          // dilation radius of the edge scores
     double az0, dphi, rmin2, rmax2;
     double thr[3];
     double cos_min;
@@ -77,6 +80,7 @@ struct Workspace {
                           // ring i and firing j, -1 if not used (point labels only)
     int32_t* cvid;        // per cell (cell_off + cell): its vertex id, -1 if empty (point labels only)
     int32_t* segsize;     // per label (cell_off + label - 1): vertices carrying it (segment removal)
+    int32_t* vtruth;      // per vertex (cell_off + vertex): truth id of its point (edge scores)
     const double* elev;   // ring elevations, per frame at elev_off
 };
 
@@ -95,10 +99,11 @@ struct LaunchCfg {
     int max_vitems;
     int max_border;  // border slots
     int max_frames;
-    bool post;       // launch the segment-removal / point-label stage
+    bool post = false;   // launch the segment-removal / point-label stage
+    bool score = false;  // launch the edge-score stage
 };
 
-constexpr int N_STAGES = 10;  // bin, count, geom, cc, merge, compress, flatten, scan, label, post
+constexpr int N_STAGES = 11;  // bin, count, geom, cc, merge, compress, flatten, scan, label, post, score
 
 // Tile shapes (cells per tile, threads per tile workgroup) the kernels are built for.
 bool tile_shape_supported(int tile_cells, int tile_threads);

@@ -20,6 +20,7 @@
 //   k_scan     per frame: roots before each labelling item (their rank base)
 //   k_resolve  label = 1 + rank of the vertex's root; segment sizes
 //   k_post     (when asked for) segment removal and every input point's label  [Segmentation, last paragraph]
+//   k_score    (when asked for) edge scores of the labels against truth ids   [Section 3, evaluation]
 //
 // Algorithm 1 floods through neighbours whose normal components differ by less
 // than the thresholds; that test is symmetric, so the flood's label classes are
@@ -289,6 +290,7 @@ __global__ __launch_bounds__(NT) void k_count(const BatchHeader* __restrict__ hd
         const int64_t rbase = (int64_t)(inside ? k0 + TWe : 0) * H;
         const uint64_t* keys = ws.keys + fd->cell_off;
         const int64_t np = fd->n_points;
+        if (fd->scores && t == fd->tile_off && threadIdx.x < 4) fd->scores[threadIdx.x] = 0;
         __syncthreads();  // the previous tile's readers are done
         uint64_t key[RO];
 #pragma unroll
@@ -657,7 +659,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
 
         // 5. vertices, their points and triangle starts (and, for point labels,
         //    every own cell's vertex id)
-        if (fd->point_labels) {
+        if (fd->point_labels || fd->scores) {
             int32_t* const cvid = ws.cvid + fd->cell_off + (int64_t)k0 * H;
 #pragma unroll
             for (int r = 0; r < RN; ++r) {
@@ -678,6 +680,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
                 vo[1] = p.y;
                 vo[2] = p.z;
                 if (fd->vpoint) fd->vpoint[vid[r]] = saux[l];
+                if (fd->scores) ws.vtruth[fd->cell_off + vid[r]] = fd->truth[saux[l]];
                 saux[l] = ltr[r];
             }
         }
@@ -1315,6 +1318,102 @@ __global__ __launch_bounds__(NT) void k_post(const BatchHeader* __restrict__ hdr
     }
 }
 
+// Edge scores of the final labels against the truth ids (the evaluation of
+// Section 3: segment edges and ground-truth edges, each dilated by R lattice
+// steps).  Per tile, columns lc = -R-1 .. TWe+R are staged in LDS (label and
+// truth id of each cell's vertex, label -1 for an empty cell); edge flags are
+// formed for lc = -R .. TWe+R-1 from the six mesh neighbours; every own edge
+// cell then looks for an edge of the other kind in its (2R+1) x (2R+1) window.
+// A closed sweep maps the staged columns around the cylinder, so a column may
+// be staged twice when the tile's window spans the whole sweep; "any edge in
+// the window" is unaffected.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_score(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int NS = MAX_TILE_CELLS + (2 * MAX_SCORE_RADIUS + 2) * MAX_RINGS;
+    __shared__ int s_lab[NS];
+    __shared__ int s_tru[NS];
+    __shared__ uint8_t s_flag[NS];
+    __shared__ unsigned long long s_sum[4];
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    const int lane = lane_id();
+    for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
+        if (!fd->scores) continue;
+        const int H = fd->H, Wp = fd->Wp, R = fd->score_r;
+        const float inv_h = 1.0f / (float)H;
+        const int k0 = (t - fd->tile_off) * fd->TW;
+        const int TWe = min(fd->TW, Wp - k0);
+        const int n = (TWe + 2 * R + 2) * H;
+        const int32_t* cvid = ws.cvid + fd->cell_off;
+        const int32_t* vtruth = ws.vtruth + fd->cell_off;
+        __syncthreads();  // LDS of the previous tile is free
+        if (threadIdx.x < 4) s_sum[threadIdx.x] = 0;
+        for (int x = threadIdx.x; x < n; x += NT) {
+            const int c = div_small(x, inv_h), i = x - c * H;
+            int k = k0 + c - R - 1;
+            int lab = -1, tru = -1;
+            bool in = true;
+            if (k < 0 || k >= Wp) {
+                if (fd->wrap) k = ((k % Wp) + Wp) % Wp;
+                else in = false;
+            }
+            if (in) {
+                const int v = cvid[(int64_t)k * H + i];
+                if (v >= 0) {
+                    lab = fd->labels[v];
+                    tru = vtruth[v];
+                }
+            }
+            s_lab[x] = lab;
+            s_tru[x] = tru;
+        }
+        __syncthreads();
+        for (int x = H + (int)threadIdx.x; x < n - H; x += NT) {
+            const int i = x - div_small(x, inv_h) * H;
+            const int lab = s_lab[x], tru = s_tru[x];
+            int fl = 0;
+            if (lab >= 0) {
+                // neighbours A..F: (i+1,c) (i+1,c+1) (i,c+1) (i-1,c) (i-1,c-1) (i,c-1)
+                const int up = i > 0, dn = i + 1 < H;
+                const int nb[6] = {x + 1, x + H + 1, x + H, x - 1, x - H - 1, x - H};
+                const bool ok[6] = {(bool)dn, (bool)dn, true, (bool)up, (bool)up, true};
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    if (!ok[q]) continue;
+                    const int l2 = s_lab[nb[q]];
+                    if (l2 < 0) continue;
+                    fl |= (l2 != lab ? 1 : 0) | (s_tru[nb[q]] != tru ? 2 : 0);
+                }
+            }
+            s_flag[x] = (uint8_t)fl;
+        }
+        __syncthreads();
+        int cnt[4] = {0, 0, 0, 0};
+        for (int x = (R + 1) * H + (int)threadIdx.x; x < (R + 1 + TWe) * H; x += NT) {
+            const int fl = s_flag[x];
+            if (!fl) continue;
+            const int i = x - div_small(x, inv_h) * H;
+            const int ia = max(-R, -i), ib = min(R, H - 1 - i);
+            int any = 0;
+            for (int dc = -R; dc <= R; ++dc)
+                for (int di = ia; di <= ib; ++di) any |= s_flag[x + dc * H + di];
+            cnt[0] += fl & 1;
+            cnt[1] += (fl >> 1) & 1;
+            cnt[2] += (fl & 1) && (any & 2);
+            cnt[3] += (fl & 2) && (any & 1);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int w = wave_sum(cnt[q]);
+            if (lane == 0 && w) atomicAdd(&s_sum[q], (unsigned long long)w);
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && s_sum[threadIdx.x])
+            atomicAdd(reinterpret_cast<unsigned long long*>(fd->scores) + threadIdx.x, s_sum[threadIdx.x]);
+    }
+}
+
 // The three tile kernels for one tile shape (TT threads, MAXC cells per tile).
 template <int TT, int MAXC>
 void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_tiles, int g_cc, hipStream_t stream,
@@ -1375,6 +1474,8 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
         const int g_post = (int)(items < 2 * (int64_t)cfg.grid ? (items > 0 ? items : 1) : 2 * (int64_t)cfg.grid);
         k_post<NT><<<g_post, NT, 0, stream>>>(d_hdr, ws);
     }
+    mark();
+    if (cfg.score) k_score<NT><<<g_cc, NT, 0, stream>>>(d_hdr, ws);
     mark();
     const hipError_t le = hipGetLastError();
     return le != hipSuccess ? le : e;

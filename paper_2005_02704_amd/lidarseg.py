@@ -32,8 +32,9 @@ LIDAR_PRED_COSINE = 1
 EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lidar_last_error",
            "lidar_query_sizes", "lidar_mesh_segment", "lidar_ctx_set_tuning", "lidar_ctx_set_profiling",
            "lidar_ctx_stage_times")
-LIDAR_N_STAGES = 10
-STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post")
+LIDAR_N_STAGES = 11
+STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post", "score")
+LIDAR_MAX_SCORE_RADIUS = 8
 
 
 class LidarError(RuntimeError):
@@ -50,19 +51,20 @@ class lidar_sensor_t(ctypes.Structure):
 
 class lidar_frame_t(ctypes.Structure):
     _fields_ = [("sensor", ctypes.POINTER(lidar_sensor_t)), ("xyz", ctypes.c_void_p),
-                ("n_points", ctypes.c_int64), ("normals_in", ctypes.c_void_p)]
+                ("n_points", ctypes.c_int64), ("normals_in", ctypes.c_void_p), ("truth_ids", ctypes.c_void_p)]
 
 
 class lidar_params_t(ctypes.Structure):
     _fields_ = [("r_min", ctypes.c_double), ("r_max", ctypes.c_double), ("thr", ctypes.c_double * 3),
-                ("predicate", ctypes.c_int32), ("min_segment", ctypes.c_int32), ("cos_min", ctypes.c_double)]
+                ("predicate", ctypes.c_int32), ("min_segment", ctypes.c_int32), ("cos_min", ctypes.c_double),
+                ("score_radius", ctypes.c_int32)]
 
 
 class lidar_result_t(ctypes.Structure):
     _fields_ = [("vertices", ctypes.c_void_p), ("normals", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("triangles", ctypes.c_void_p),
                 ("vertex_point", ctypes.c_void_p), ("counts", ctypes.c_void_p),
-                ("point_labels", ctypes.c_void_p)]
+                ("point_labels", ctypes.c_void_p), ("edge_counts", ctypes.c_void_p)]
 
 
 _lib = None
@@ -144,8 +146,10 @@ def lidar_query_sizes(sensor: SensorGeometry):
 class Outputs:
     """Caller-owned device outputs of one frame (torch tensors at full capacity)."""
 
-    def __init__(self, sensor: SensorGeometry, device, with_vertex_point=True, n_points: int = 0):
-        """n_points > 0 also allocates point_labels (every input point's label)."""
+    def __init__(self, sensor: SensorGeometry, device, with_vertex_point=True, n_points: int = 0,
+                 scores: bool = False):
+        """n_points > 0 also allocates point_labels (every input point's label);
+        scores allocates edge_counts (edge scores against the frame's truth ids)."""
         import torch
         V, T = lidar_query_sizes(sensor)
         self.vertices = torch.empty((max(V, 1), 3), dtype=torch.float32, device=device)
@@ -155,13 +159,15 @@ class Outputs:
         self.vertex_point = torch.empty(max(V, 1), dtype=torch.int32, device=device) if with_vertex_point else None
         self.counts = torch.zeros(3, dtype=torch.int64, device=device)
         self.point_labels = torch.empty(n_points, dtype=torch.int32, device=device) if n_points > 0 else None
+        self.edge_counts = torch.zeros(4, dtype=torch.int64, device=device) if scores else None
 
     def c_struct(self) -> lidar_result_t:
         return lidar_result_t(self.vertices.data_ptr(), self.normals.data_ptr(), self.labels.data_ptr(),
                               self.triangles.data_ptr(),
                               self.vertex_point.data_ptr() if self.vertex_point is not None else None,
                               self.counts.data_ptr(),
-                              self.point_labels.data_ptr() if self.point_labels is not None else None)
+                              self.point_labels.data_ptr() if self.point_labels is not None else None,
+                              self.edge_counts.data_ptr() if self.edge_counts is not None else None)
 
     def trimmed(self):
         """Views cut to the counts (synchronises with the device to read them)."""
@@ -171,7 +177,9 @@ class Outputs:
         return dict(vertices=self.vertices[:V], normals=self.normals[:V], labels=self.labels[:V],
                     triangles=self.triangles[:T],
                     vertex_point=self.vertex_point[:V] if self.vertex_point is not None else None,
-                    point_labels=self.point_labels, counts=(V, T, K))
+                    point_labels=self.point_labels, counts=(V, T, K),
+                    edge_counts=tuple(int(x) for x in self.edge_counts.cpu()) if self.edge_counts is not None
+                    else None)
 
 
 class LidarContext:
@@ -220,12 +228,15 @@ class LidarContext:
         frames = (lidar_frame_t * n)()
         results = (lidar_result_t * n)()
         keep = []
-        for f, (xyz, sensor, normals_in) in enumerate(inputs):
+        for f, item in enumerate(inputs):
+            xyz, sensor, normals_in = item[:3]
+            truth = item[3] if len(item) > 3 else None
             sc = sensor.c_struct()
             keep.append(sc)
             frames[f] = lidar_frame_t(ctypes.pointer(sc), xyz.data_ptr() if xyz.numel() else None,
                                       int(xyz.shape[0]),
-                                      normals_in.data_ptr() if normals_in is not None else None)
+                                      normals_in.data_ptr() if normals_in is not None else None,
+                                      truth.data_ptr() if truth is not None and truth.numel() else None)
             results[f] = outputs[f].c_struct()
         return (frames, n, params, results, keep)
 
@@ -242,21 +253,34 @@ class LidarContext:
 
 
 def make_params(r_min=1.0, r_max=60.0, thr=(0.2, 0.2, 0.2), predicate=LIDAR_PRED_COMPONENTS, cos_min=0.0,
-                min_segment=0) -> lidar_params_t:
+                min_segment=0, score_radius=1) -> lidar_params_t:
     return lidar_params_t(float(r_min), float(r_max), (ctypes.c_double * 3)(*[float(t) for t in thr]),
-                          int(predicate), int(min_segment), float(cos_min))
+                          int(predicate), int(min_segment), float(cos_min), int(score_radius))
+
+
+def precision_recall_f1(edge_counts):
+    """Precision, recall and F1 of one frame's edge counts (segment edges, truth
+    edges, found, recalled); a side without edges scores 1 when the other has
+    none either, else 0."""
+    n_seg, n_tru, found, recalled = (int(x) for x in edge_counts)
+    p = found / n_seg if n_seg else (1.0 if n_tru == 0 else 0.0)
+    r = recalled / n_tru if n_tru else (1.0 if n_seg == 0 else 0.0)
+    return p, r, (2 * p * r / (p + r) if p + r > 0 else 0.0)
 
 
 def lidar_mesh_segment(ctx: LidarContext, inputs, params: lidar_params_t | None = None,
-                       launch: str = "batched", stream=None, with_vertex_point=True, point_labels=False):
-    """Convenience: inputs = [(xyz cuda float32 [N,3], SensorGeometry, normals_in or None)].
+                       launch: str = "batched", stream=None, with_vertex_point=True, point_labels=False,
+                       scores=False):
+    """Convenience: inputs = [(xyz cuda float32 [N,3], SensorGeometry, normals_in or None
+    [, truth ids cuda int32 [N]])]; scores asks for the edge counts (needs truth ids).
 
     Allocates outputs, enqueues the call and returns the Outputs objects (call
     .trimmed() to synchronise and cut them to their counts)."""
     import torch
     params = params or make_params()
     dev = torch.device("cuda", ctx.device)
-    outs = [Outputs(s, dev, with_vertex_point, int(x.shape[0]) if point_labels else 0) for (x, s, _n) in inputs]
+    outs = [Outputs(item[1], dev, with_vertex_point, int(item[0].shape[0]) if point_labels else 0, scores)
+            for item in inputs]
     prep = ctx.prepare(inputs, params, outs)
     ctx.lidar_mesh_segment(prep, stream=stream, launch=launch)
     return outs

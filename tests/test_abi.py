@@ -41,3 +41,28 @@ def test_query_sizes_and_validation_on_host():
     geo = lp.SensorGeometry(np.radians(np.linspace(15, -15, 16)), 2, 1, wrap=1)
     with pytest.raises(lp.LidarError):
         lp.lidar_query_sizes(geo)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every field offset and struct size of the ctypes binding equals the C
+    compiler's for include/lidarseg.h."""
+    import subprocess
+    from paper_2005_02704_amd import lidarseg as b
+    structs = [b.lidar_sensor_t, b.lidar_frame_t, b.lidar_params_t, b.lidar_result_t]
+    lines = []
+    for st in structs:
+        name = st.__name__
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in st._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lidarseg.h\"\nint main(void) {\n"
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[f"{name} size"]) == ctypes.sizeof(st), name
+        for fname, _ in st._fields_:
+            assert int(got[f"{name} {fname}"]) == getattr(st, fname).offset, (name, fname)
