@@ -67,6 +67,16 @@ __device__ __forceinline__ bool occupied(uint64_t key, int64_t n_points) {
     return key != KEY_EMPTY && (int64_t)(uint32_t)key < n_points;
 }
 
+// The point index of cell c's key: the key's low 32 bits (0xFFFFFFFF when the
+// cell is empty).  Reading the index alone keeps half the registers.
+__device__ __forceinline__ uint32_t key_index(const uint64_t* keys, int64_t c) {
+    return reinterpret_cast<const uint32_t*>(keys)[2 * c];
+}
+
+__device__ __forceinline__ bool occupied_index(uint32_t idx, int64_t n_points) {
+    return (int64_t)idx < n_points;
+}
+
 // Largest frame f with F[f].*off <= x (offsets ascend with f).
 template <int32_t FrameDesc::*OFF>
 __device__ __forceinline__ int frame_of(const FrameDesc* F, int nf, int x) {
@@ -292,18 +302,18 @@ __global__ __launch_bounds__(NT) void k_count(const BatchHeader* __restrict__ hd
         const int64_t np = fd->n_points;
         if (fd->scores && t == fd->tile_off && threadIdx.x < 4) fd->scores[threadIdx.x] = 0;
         __syncthreads();  // the previous tile's readers are done
-        uint64_t key[RO];
+        uint32_t key[RO];
 #pragma unroll
         for (int r = 0; r < RO; ++r) {
             const int l = threadIdx.x + r * NT;
-            key[r] = KEY_EMPTY;
-            if (l < nown) key[r] = keys[(int64_t)k0 * H + l];
-            else if (l < nown + H && right) key[r] = keys[rbase + (l - nown)];
+            key[r] = ~0u;
+            if (l < nown) key[r] = key_index(keys, (int64_t)k0 * H + l);
+            else if (l < nown + H && right) key[r] = key_index(keys, rbase + (l - nown));
         }
 #pragma unroll
         for (int r = 0; r < RO; ++r) {
             const int l = threadIdx.x + r * NT;
-            if (l < nown + H) socc[l] = occupied(key[r], np) ? 1 : 0;
+            if (l < nown + H) socc[l] = occupied_index(key[r], np) ? 1 : 0;
         }
         __syncthreads();
         int nv = 0, nt = 0;
@@ -419,44 +429,40 @@ __device__ __forceinline__ double sqrt_dp(double x) {
 // Branch-free: an absent neighbour (off the ring range, or an empty cell, whose
 // coordinates are NaN) is replaced by the vertex itself, so its edge vector is
 // zero, its cross products vanish and its length is a tiny positive number.
-// Neighbours are visited once, in cycle order, keeping only the previous and the
-// first edge vector live.
+// Neighbours are visited once in cycle order, keeping only the previous edge
+// live; the first edge is formed again to close the cycle (same arithmetic, same
+// bits), which keeps the register footprint small.
+__device__ __forceinline__ void vertex_edge(const float4* sc, int lx, int t, int H, bool up, bool dn, float4 P,
+                                            double& vx, double& vy, double& vz, double& lv, bool& pv) {
+    const int off = t == 0 ? 1 : t == 1 ? H + 1 : t == 2 ? H : t == 3 ? -1 : t == 4 ? -H - 1 : -H;
+    const bool inr = (t <= 1) ? dn : (t == 3 || t == 4) ? up : true;
+    const float4 Q = sc[inr ? lx + off : lx];
+    pv = inr && (Q.x == Q.x);
+    vx = (double)(pv ? Q.x : P.x) - (double)P.x;
+    vy = (double)(pv ? Q.y : P.y) - (double)P.y;
+    vz = (double)(pv ? Q.z : P.z) - (double)P.z;
+    lv = sqrt_dp(fma(vx, vx, fma(vy, vy, fma(vz, vz, LEN2_FLOOR))));
+}
+
 __device__ __forceinline__ void vertex_normal(const float4* sc, int lx, int i, int H, float& onx, float& ony,
                                               float& onz) {
     const bool up = i >= 1, dn = i + 1 < H;
-    const int off[6] = {1, H + 1, H, -1, -H - 1, -H};
-    const bool inr[6] = {dn, dn, true, up, up, true};
     const float4 P = sc[lx];
-    const double px = P.x, py = P.y, pz = P.z;
-    double fx = 0.0, fy = 0.0, fz = 0.0, lf = 0.0;
-    bool pf = false;
-    double ux = 0.0, uy = 0.0, uz = 0.0, lu = 0.0;
-    bool pu = false;
+    double ux, uy, uz, lu;
+    bool pu;
+    vertex_edge(sc, lx, 0, H, up, dn, P, ux, uy, uz, lu, pu);
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool any = false;
 #pragma unroll
-    for (int t = 0; t <= 6; ++t) {
+    for (int t = 1; t <= 6; ++t) {
         double vx, vy, vz, lv;
         bool pv;
-        if (t < 6) {
-            const float4 Q = sc[inr[t] ? lx + off[t] : lx];
-            pv = inr[t] && (Q.x == Q.x);
-            vx = (double)(pv ? Q.x : P.x) - px;
-            vy = (double)(pv ? Q.y : P.y) - py;
-            vz = (double)(pv ? Q.z : P.z) - pz;
-            lv = sqrt_dp(fma(vx, vx, fma(vy, vy, fma(vz, vz, LEN2_FLOOR))));
-        } else {
-            vx = fx; vy = fy; vz = fz; lv = lf; pv = pf;
-        }
-        if (t == 0) {
-            fx = vx; fy = vy; fz = vz; lf = lv; pf = pv;
-        } else {
-            const double w = rcp_dp(lu + lv);
-            ax = fma(w, fma(uy, vz, -uz * vy), ax);
-            ay = fma(w, fma(uz, vx, -ux * vz), ay);
-            az = fma(w, fma(ux, vy, -uy * vx), az);
-            any |= pu && pv;
-        }
+        vertex_edge(sc, lx, t % 6, H, up, dn, P, vx, vy, vz, lv, pv);
+        const double w = rcp_dp(lu + lv);
+        ax = fma(w, fma(uy, vz, -uz * vy), ax);
+        ay = fma(w, fma(uz, vx, -ux * vz), ay);
+        az = fma(w, fma(ux, vy, -uy * vx), az);
+        any |= pu && pv;
         ux = vx; uy = vy; uz = vz; lu = lv; pu = pv;
     }
     const double n2 = ax * ax + ay * ay + az * az;
@@ -687,39 +693,41 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
         __syncthreads();
 
         // 6. triangles T_a = (p, A, B), T_b = (p, B, C) of each own anchor, and
-        //    the normals of the own vertices (or the given ones, copied)
+        //    the normals of the own vertices (or the given ones, copied).  Vertex
+        //    ids and triangle starts are read back from LDS, so no per-round
+        //    state stays in registers across the normal stencil.
         {
-            int i = i0;
-#pragma unroll
-            for (int r = 0; r < RN; ++r) {
-                const int l = threadIdx.x + NT * r;
-                const int ir = i;
-                i += step_i;
-                if (i >= H) i -= H;
-                if (l >= nown || vid[r] < 0) continue;
+            int ir = i0;
+#pragma unroll 1
+            for (int l = threadIdx.x; l < nown; l += NT) {
                 const int lx = l + H;
-                if (ir + 1 < H) {
+                const int i = ir;
+                ir += step_i;
+                if (ir >= H) ir -= H;
+                const int v = vid_of(sc[lx]);
+                if (v < 0) continue;
+                if (i + 1 < H) {
                     const int a = vid_of(sc[lx + 1]), b = vid_of(sc[lx + H + 1]), c = vid_of(sc[lx + H]);
                     int ti = saux[l];
                     if (a >= 0 && b >= 0) {
                         int32_t* to = fd->tris + 3 * (int64_t)ti;
-                        to[0] = vid[r]; to[1] = a; to[2] = b;
+                        to[0] = v; to[1] = a; to[2] = b;
                         ++ti;
                     }
                     if (b >= 0 && c >= 0) {
                         int32_t* to = fd->tris + 3 * (int64_t)ti;
-                        to[0] = vid[r]; to[1] = b; to[2] = c;
+                        to[0] = v; to[1] = b; to[2] = c;
                     }
                 }
                 float nx_, ny_, nz_;
                 if (nin) {
-                    nx_ = nin[3 * (int64_t)vid[r]];
-                    ny_ = nin[3 * (int64_t)vid[r] + 1];
-                    nz_ = nin[3 * (int64_t)vid[r] + 2];
+                    nx_ = nin[3 * (int64_t)v];
+                    ny_ = nin[3 * (int64_t)v + 1];
+                    nz_ = nin[3 * (int64_t)v + 2];
                 } else {
-                    vertex_normal(sc, lx, ir, H, nx_, ny_, nz_);
+                    vertex_normal(sc, lx, i, H, nx_, ny_, nz_);
                 }
-                float* no = fd->normals + 3 * (int64_t)vid[r];
+                float* no = fd->normals + 3 * (int64_t)v;
                 no[0] = nx_;
                 no[1] = ny_;
                 no[2] = nz_;
@@ -741,13 +749,17 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
     constexpr int NW = NT / 64;
     constexpr int RN = (NC + NT - 1) / NT;
     static_assert(RN * NW <= 64, "one lane per (round, wave) in the prefix scan");
-    __shared__ float4 sn[NC];
+    constexpr int NB = (3 * NC > 2 * MAXC) ? 3 * NC : 2 * MAXC;
+    __shared__ int s_buf[NB];         // normals (3 floats per cell), later the join list
+    __shared__ int svid[NC];          // vertex id of own cells and the right column, -1 empty
     __shared__ int sparent[MAXC];     // union-find parent of own cells
     __shared__ uint8_t sedge[MAXC];   // similar joins of own cells: bit 0 A (down), 1 C (right), 2 B (diagonal)
     __shared__ int s_cnt[RN * NW];
     __shared__ int s_misc[2];         // vertex base, own vertices
-    __shared__ int s_join[2 * MAXC];  // unions inside the tile: cell | cell << 16
     __shared__ int s_nj;
+    float* const sn3 = reinterpret_cast<float*>(s_buf);
+    int* const s_join = s_buf;        // unions inside the tile: cell | cell << 16
+    auto nrm_of = [&](int l) { return make_float4(sn3[3 * l], sn3[3 * l + 1], sn3[3 * l + 2], 0.0f); };
 
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
@@ -813,13 +825,16 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
             const int l = threadIdx.x + NT * r;
             if (l >= nscan) continue;
             const float q = __builtin_nanf("");
-            float4 a = make_float4(q, q, q, __int_as_float(vid[r]));
+            float ax = q, ay = q, az = q;
             if (vid[r] >= 0) {
                 const float x = nrm[3 * (int64_t)vid[r]], y = nrm[3 * (int64_t)vid[r] + 1],
                             z = nrm[3 * (int64_t)vid[r] + 2];
-                if (!(x == 0.0f && y == 0.0f && z == 0.0f)) { a.x = x; a.y = y; a.z = z; }
+                if (!(x == 0.0f && y == 0.0f && z == 0.0f)) { ax = x; ay = y; az = z; }
             }
-            sn[l] = a;
+            sn3[3 * l] = ax;
+            sn3[3 * l + 1] = ay;
+            sn3[3 * l + 2] = az;
+            svid[l] = vid[r];
         }
         __syncthreads();
 
@@ -834,12 +849,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
                 i += step_i;
                 if (i >= H) i -= H;
                 if (l >= nown) continue;
-                const float4 a = sn[l];
+                const float4 a = nrm_of(l);
                 const bool dn = ir + 1 < H;
                 int e = 0;
-                if (dn && similar(a, sn[l + 1], sim)) e |= 1;
-                if (similar(a, sn[l + H], sim)) e |= 2;
-                if (dn && similar(a, sn[l + H + 1], sim)) e |= 4;
+                if (dn && similar(a, nrm_of(l + 1), sim)) e |= 1;
+                if (similar(a, nrm_of(l + H), sim)) e |= 2;
+                if (dn && similar(a, nrm_of(l + H + 1), sim)) e |= 4;
                 sedge[l] = (uint8_t)e;
             }
         }
@@ -878,6 +893,28 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
             }
         }
 
+        // 6. joins leaving through the right edge, with the same implication
+        //    rules (A joins of the right column from its normals), into the
+        //    tile's border slots: 2i for the C join of ring i, 2i+1 for its B join
+        {
+            int2* const slots = ws.border + fd->border_off + (int64_t)lt * 2 * H;
+            for (int i = threadIdx.x; i < H; i += NT) {
+                const int l = (TWe - 1) * H + i;
+                const int e = sedge[l];
+                const int a = cell_off + svid[l];
+                int2 jc = make_int2(-1, -1), jb = make_int2(-1, -1);
+                if ((e & 2) && !(i >= 1 && (sedge[l - 1] & 3) == 3 && similar(nrm_of(l - 1 + H), nrm_of(l + H), sim)))
+                    jc = make_int2(a, cell_off + svid[l + H]);
+                if ((e & 4) && !(((e & 1) && (sedge[l + 1] & 2)) ||
+                                 ((e & 2) && similar(nrm_of(l + H), nrm_of(l + H + 1), sim))))
+                    jb = make_int2(a, cell_off + svid[l + H + 1]);
+                slots[2 * i] = jc;
+                slots[2 * i + 1] = jb;
+            }
+        }
+
+        __syncthreads();  // the normals are read; their space becomes the join list
+
         // 5. unions across columns inside the tile.  A right (C) join is implied
         //    when the cell above has one and both cells continue their runs
         //    downwards; a diagonal (B) join is implied by A then C, or C then A.
@@ -915,26 +952,6 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
         }
         __syncthreads();
 
-        // 6. joins leaving through the right edge, with the same implication
-        //    rules (A joins of the right column from its normals), into the
-        //    tile's border slots: 2i for the C join of ring i, 2i+1 for its B join
-        {
-            int2* const slots = ws.border + fd->border_off + (int64_t)lt * 2 * H;
-            for (int i = threadIdx.x; i < H; i += NT) {
-                const int l = (TWe - 1) * H + i;
-                const int e = sedge[l];
-                const int a = cell_off + vid_of(sn[l]);
-                int2 jc = make_int2(-1, -1), jb = make_int2(-1, -1);
-                if ((e & 2) && !(i >= 1 && (sedge[l - 1] & 3) == 3 && similar(sn[l - 1 + H], sn[l + H], sim)))
-                    jc = make_int2(a, cell_off + vid_of(sn[l + H]));
-                if ((e & 4) && !(((e & 1) && (sedge[l + 1] & 2)) ||
-                                 ((e & 2) && similar(sn[l + H], sn[l + H + 1], sim))))
-                    jb = make_int2(a, cell_off + vid_of(sn[l + H + 1]));
-                slots[2 * i] = jc;
-                slots[2 * i + 1] = jb;
-            }
-        }
-
         // 7. local roots: the smallest cell of each local tree (no writes while reading)
         int* const forest = ws.forest;
 #pragma unroll
@@ -943,7 +960,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
             if (l >= nown || vid[r] < 0) continue;
             int x = sparent[l];
             for (int it = 0; it < nown && sparent[x] != x; ++it) x = sparent[x];
-            forest[cell_off + vid[r]] = cell_off + vid_of(sn[x]);
+            forest[cell_off + vid[r]] = cell_off + svid[x];
         }
     }
 }
