@@ -399,8 +399,11 @@ __device__ __forceinline__ bool similar(float4 a, float4 b, const SimTest& q) {
         const double d = ((double)a.x * (double)b.x + (double)a.y * (double)b.y) + (double)a.z * (double)b.z;
         return d > q.cmin;
     }
-    return fabs((double)a.x - (double)b.x) < q.tx && fabs((double)a.y - (double)b.y) < q.ty &&
-           fabs((double)a.z - (double)b.z) < q.tz;
+    // all three comparisons, combined without branches
+    const bool x = fabs((double)a.x - (double)b.x) < q.tx;
+    const bool y = fabs((double)a.y - (double)b.y) < q.ty;
+    const bool z = fabs((double)a.z - (double)b.z) < q.tz;
+    return x & y & z;
 }
 
 // FP64 reciprocal, reciprocal square root and square root: the hardware estimate
@@ -849,12 +852,15 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
                 i += step_i;
                 if (i >= H) i -= H;
                 if (l >= nown) continue;
-                const float4 a = nrm_of(l);
+                // every test is evaluated (off the ring range against the cell
+                // itself) and masked, so the wave does not branch
                 const bool dn = ir + 1 < H;
-                int e = 0;
-                if (dn && similar(a, nrm_of(l + 1), sim)) e |= 1;
-                if (similar(a, nrm_of(l + H), sim)) e |= 2;
-                if (dn && similar(a, nrm_of(l + H + 1), sim)) e |= 4;
+                const float4 a = nrm_of(l);
+                const float4 qa = nrm_of(dn ? l + 1 : l);
+                const float4 qc = nrm_of(l + H);
+                const float4 qb = nrm_of(dn ? l + H + 1 : l);
+                const int e = (int)(dn & similar(a, qa, sim)) | ((int)similar(a, qc, sim) << 1) |
+                              ((int)(dn & similar(a, qb, sim)) << 2);
                 sedge[l] = (uint8_t)e;
             }
         }
@@ -868,7 +874,8 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
 #pragma unroll
             for (int r = 0; r < RN; ++r) {
                 const int l = threadIdx.x + NT * r;
-                const bool start = !(l < nown && i >= 1 && (sedge[l - 1] & 1));
+                const int above = sedge[min(max(l - 1, 0), MAXC - 1)];
+                const bool start = !((l < nown) & (i >= 1) & ((above & 1) != 0));
                 i += step_i;
                 if (i >= H) i -= H;
                 const uint64_t S = __ballot(start);
@@ -928,12 +935,15 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
                 const int ir = i;
                 i += step_i;
                 if (i >= H) i -= H;
-                bool jc = false, jb = false;
-                if (l + H < nown) {   // the right neighbour column is own
-                    const int e = sedge[l];
-                    jc = (e & 2) && !(ir >= 1 && (sedge[l - 1] & 3) == 3 && (sedge[l - 1 + H] & 1));
-                    jb = (e & 4) && !(((e & 1) && (sedge[l + 1] & 2)) || ((e & 2) && (sedge[l + H] & 1)));
-                }
+                // (branch-free: every read is in range, the results are masked)
+                const bool inside = l + H < nown;   // the right neighbour column is own
+                const int lc = inside ? l : 0;
+                const int e = sedge[lc];
+                const int eu = sedge[lc >= 1 ? lc - 1 : 0], eur = sedge[lc >= 1 ? lc - 1 + H : 0];
+                const int ed = sedge[lc + 1], er = sedge[lc + H];
+                const bool jc = inside & ((e & 2) != 0) & !((ir >= 1) & ((eu & 3) == 3) & ((eur & 1) != 0));
+                const bool jb = inside & ((e & 4) != 0) &
+                                !((((e & 1) != 0) & ((ed & 2) != 0)) | (((e & 2) != 0) & ((er & 1) != 0)));
                 const uint64_t mc = __ballot(jc), mb = __ballot(jb);
                 const int n = __popcll(mc) + __popcll(mb);
                 if (n) {
