@@ -57,6 +57,15 @@ __device__ __forceinline__ int wave_sum(int x) {
     return x;
 }
 
+// A frame descriptor's pointer as a global-memory pointer.  Pointers read from
+// device memory are generic to the compiler, which then emits flat accesses;
+// those also count against the LDS wait counter, so every wait for an LDS read
+// would wait for them as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ const FrameDesc* frames_of(const BatchHeader* h) {
     return reinterpret_cast<const FrameDesc*>(h + 1);
 }
@@ -109,14 +118,33 @@ __device__ __forceinline__ int nearest_ring(const double* e, int H, double el) {
     return (d_dn < d_up) ? lo : lo - 1;
 }
 
-// The FP64 decisions, kept out of line: they run only for points whose FP32
-// estimate falls inside a guard band.
+// The FP64 decisions, out of line.  They run only for points whose FP32
+// estimate falls inside a guard band, in a pass after the fast one.
 __device__ __attribute__((noinline)) int ring_fp64(const double* e, int H, double z, double rho2) {
     return nearest_ring(e, H, atan2(z, sqrt(rho2)));
 }
 
 __device__ __attribute__((noinline)) int firing_fp64(double x, double y, double az0, double dphi) {
     return (int)round((atan2(y, x) - az0) / dphi);
+}
+
+// The cell of a used point (firing j in [0, W), ring i), its key, and the record
+// j * H + i for point labels: shared by the fast and the exact pass.
+__device__ __forceinline__ void bin_store(unsigned long long* keys, int32_t* pcell, int64_t p, int ring, int j, int W,
+                                          int H, int s, double r2) {
+    if (j < 0) j += W;
+    if (j < 0) j += W;
+    if (j >= W) j -= W;
+    if (j >= W) j -= W;
+    if (pcell) pcell[p] = j * H + ring;
+    int k = j;
+    if (s > 1) {
+        k = j / s;
+        if (k * s != j) return;
+    }
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint((float)r2) << 32) | (unsigned long long)(uint32_t)p;
+    atomicMin(keys + (int64_t)k * H + ring, key);
 }
 
 // atan(q) ~= q * P(q^2) on [0, 1]: a degree-8 polynomial in q^2 fitted for this
@@ -156,7 +184,7 @@ constexpr int RING_LUT = 1024;   // buckets of the ring lookup table (tan of ele
 // farther than a guard band from every decision boundary the FP64 decision is
 // the same and is not computed.  Inside a band the FP64 expression decides.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr, Workspace ws) {
+__global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int PPT = POINT_BLOCK / NT;  // points per thread per item
     __shared__ double s_elev[MAX_RINGS];
     __shared__ float s_T[MAX_RINGS];       // s_T[i]: tan of the midpoint of rings i and i+1 (descending)
@@ -203,7 +231,7 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
         const float inv_dphif = (float)(1.0 / dphi);
         const bool col_fast = W <= COL_GUARD_MAX_W;
         const float lo = s_lo, inv = s_inv;
-        const float* __restrict__ xyz = fd->xyz;
+        const auto xyz = gmem(fd->xyz);
         unsigned long long* keys = reinterpret_cast<unsigned long long*>(ws.keys + fd->cell_off);
         const int64_t p0 = (int64_t)(b - fd->pblk_off) * POINT_BLOCK + threadIdx.x;
         const int64_t np = fd->n_points;
@@ -220,54 +248,52 @@ __global__ __launch_bounds__(NT) void k_bin(const BatchHeader* __restrict__ hdr,
             }
         }
         int32_t* const pcell = fd->point_labels ? ws.pcell + fd->pt_off : nullptr;
+        // fast pass: FP32 estimates; a point inside a guard band is only flagged
+        uint32_t hard = 0;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
             const int64_t p = p0 + r * NT;
             const float xf = px[r], yf = py[r], zf = pz[r];
-            int rec = -1;   // j * H + i of a used point (full resolution), for its label later
-            do {
-                if (!(isfinite(xf) && isfinite(yf) && isfinite(zf))) break;
-                const double x = xf, y = yf, z = zf;
-                const double rho2 = x * x + y * y;   // products of floats are exact in FP64
+            bool used = isfinite(xf) && isfinite(yf) && isfinite(zf);
+            const double x = xf, y = yf, z = zf;
+            const double rho2 = x * x + y * y;   // products of floats are exact in FP64
+            const double r2 = rho2 + z * z;
+            used = used && r2 >= rmin2 && r2 <= rmax2;
+            if (!used) {
+                if (pcell && p < np) pcell[p] = -1;
+                continue;
+            }
+            // ring: t against the midpoint tangents, through the bucket table
+            const float t = zf * __builtin_amdgcn_rsqf(fmaf(xf, xf, yf * yf));
+            int ring = 0;
+            bool exact = !isfinite(t);
+            if (!exact) {
+                const float bf = fminf(fmaxf((t - lo) * inv, 0.0f), (float)(RING_LUT - 1));
+                ring = s_lut[(int)bf];
+                for (int k = 0; k < MAX_RINGS && ring > 0 && t > s_T[ring - 1]; ++k) --ring;
+                exact = (ring > 0 && fabsf(t - s_T[ring - 1]) <= 2e-6f * fabsf(s_T[ring - 1]) + 1e-7f) ||
+                        (ring + 1 < H && fabsf(t - s_T[ring]) <= 2e-6f * fabsf(s_T[ring]) + 1e-7f);
+            }
+            // firing: |az0| <= 2 pi, so the rounded firing lies in [-2W, 2W)
+            const float jff = (atan2_poly(yf, xf) - az0f) * inv_dphif;
+            exact = exact || !(col_fast && fabsf(jff - floorf(jff) - 0.5f) > COL_GUARD);
+            if (exact) {
+                hard |= 1u << r;
+                continue;
+            }
+            bin_store(keys, pcell, p, ring, (int)floorf(jff + 0.5f), W, H, s, r2);
+        }
+        // exact pass (rare): both decisions of the flagged points in FP64
+        if (hard) {
+#pragma unroll 1
+            for (int r = 0; r < PPT; ++r) {
+                if (!((hard >> r) & 1u)) continue;
+                const int64_t p = p0 + r * NT;
+                const double x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
+                const double rho2 = x * x + y * y;
                 const double r2 = rho2 + z * z;
-                if (r2 < rmin2 || r2 > rmax2) break;
-
-                // ring: t against the midpoint tangents, through the bucket table
-                const float t = zf * __builtin_amdgcn_rsqf(fmaf(xf, xf, yf * yf));
-                int ring = 0;
-                bool exact = !isfinite(t);
-                if (!exact) {
-                    const float bf = fminf(fmaxf((t - lo) * inv, 0.0f), (float)(RING_LUT - 1));
-                    ring = s_lut[(int)bf];
-                    for (int k = 0; k < MAX_RINGS && ring > 0 && t > s_T[ring - 1]; ++k) --ring;
-                    exact = (ring > 0 && fabsf(t - s_T[ring - 1]) <= 2e-6f * fabsf(s_T[ring - 1]) + 1e-7f) ||
-                            (ring + 1 < H && fabsf(t - s_T[ring]) <= 2e-6f * fabsf(s_T[ring]) + 1e-7f);
-                }
-                if (exact) ring = ring_fp64(s_elev, H, z, rho2);
-
-                // |az0| <= 2 pi, so the rounded firing lies in [-2W, 2W)
-                int j;
-                const float jff = (atan2_poly(yf, xf) - az0f) * inv_dphif;
-                if (col_fast && fabsf(jff - floorf(jff) - 0.5f) > COL_GUARD)
-                    j = (int)floorf(jff + 0.5f);
-                else
-                    j = firing_fp64(x, y, az0, dphi);
-                if (j < 0) j += W;
-                if (j < 0) j += W;
-                if (j >= W) j -= W;
-                if (j >= W) j -= W;
-                rec = j * H + ring;
-                int k = j;
-                if (s > 1) {
-                    k = j / s;
-                    if (k * s != j) break;
-                }
-                const int64_t c = (int64_t)k * H + ring;
-                const unsigned long long key =
-                    ((unsigned long long)__float_as_uint((float)r2) << 32) | (unsigned long long)(uint32_t)p;
-                atomicMin(keys + c, key);
-            } while (false);
-            if (pcell && p < np) pcell[p] = rec;
+                bin_store(keys, pcell, p, ring_fp64(s_elev, H, z, rho2), firing_fp64(x, y, az0, dphi), W, H, s, r2);
+            }
         }
     }
 }
@@ -544,8 +570,8 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
         const int nown = H * TWe;
         const int nscan = nown + H;
         const uint64_t* keys = ws.keys + fd->cell_off;
-        const float* __restrict__ xyz = fd->xyz;
-        const float* __restrict__ nin = fd->normals_in;
+        const auto xyz = gmem(fd->xyz);
+        const auto nin = gmem(fd->normals_in);
         const int64_t np = fd->n_points;
         const int step_i = NT % H, step_c = NT / H;   // (column, ring) advance per round
         const int i0 = (int)threadIdx.x - div_small(threadIdx.x, inv_h) * H;
@@ -598,7 +624,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
             for (int r = 0; r < RX; ++r) {
                 cx[r] = cy[r] = cz[r] = __builtin_nanf("");
                 if (occupied(key[r], np)) {
-                    const float* q = xyz + 3 * (int64_t)(uint32_t)key[r];
+                    const auto q = xyz + 3 * (int64_t)(uint32_t)key[r];
                     cx[r] = q[0];
                     cy[r] = q[1];
                     cz[r] = q[2];
@@ -684,12 +710,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
             sc[lx].w = __int_as_float(vid[r]);
             if (l < nown) {
                 const float4 p = sc[lx];
-                float* vo = fd->vertices + 3 * (int64_t)vid[r];
+                const auto vo = gmem(fd->vertices) + 3 * (int64_t)vid[r];
                 vo[0] = p.x;
                 vo[1] = p.y;
                 vo[2] = p.z;
-                if (fd->vpoint) fd->vpoint[vid[r]] = saux[l];
-                if (fd->scores) ws.vtruth[fd->cell_off + vid[r]] = fd->truth[saux[l]];
+                if (fd->vpoint) gmem(fd->vpoint)[vid[r]] = saux[l];
+                if (fd->scores) ws.vtruth[fd->cell_off + vid[r]] = gmem(fd->truth)[saux[l]];
                 saux[l] = ltr[r];
             }
         }
@@ -713,12 +739,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
                     const int a = vid_of(sc[lx + 1]), b = vid_of(sc[lx + H + 1]), c = vid_of(sc[lx + H]);
                     int ti = saux[l];
                     if (a >= 0 && b >= 0) {
-                        int32_t* to = fd->tris + 3 * (int64_t)ti;
+                        const auto to = gmem(fd->tris) + 3 * (int64_t)ti;
                         to[0] = v; to[1] = a; to[2] = b;
                         ++ti;
                     }
                     if (b >= 0 && c >= 0) {
-                        int32_t* to = fd->tris + 3 * (int64_t)ti;
+                        const auto to = gmem(fd->tris) + 3 * (int64_t)ti;
                         to[0] = v; to[1] = b; to[2] = c;
                     }
                 }
@@ -730,7 +756,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
                 } else {
                     vertex_normal(sc, lx, i, H, nx_, ny_, nz_);
                 }
-                float* no = fd->normals + 3 * (int64_t)v;
+                const auto no = gmem(fd->normals) + 3 * (int64_t)v;
                 no[0] = nx_;
                 no[1] = ny_;
                 no[2] = nz_;
@@ -822,7 +848,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
         number_cells<NT, RN>(vid, s_cnt, vbase, last_tile ? 0 : vbase + own_v, own_v, nown, lane, wv);
 
         // 2. normals by vertex id
-        const float* __restrict__ nrm = fd->normals;
+        const auto nrm = gmem(fd->normals);
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
             const int l = threadIdx.x + NT * r;
@@ -1163,7 +1189,7 @@ __global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ 
             const int v = v0 + r * NT + threadIdx.x;
             bool isroot = false;
             if (v < V) {
-                fd->labels[v] = cur[r] - base;
+                gmem(fd->labels)[v] = cur[r] - base;
                 isroot = cur[r] == base + v;
             }
             const uint64_t bits = __ballot(isroot);
@@ -1253,11 +1279,11 @@ __global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ 
             const int v = v0 + r * NT + threadIdx.x;
             int lab = -1;
             if (v < V) {
-                const int root = fd->labels[v];
+                const int root = gmem(fd->labels)[v];
                 const int64_t w = wframe + (root >> 6);
                 const uint64_t below = ws.rootbits[w] & ((1ull << (root & 63)) - 1ull);
                 lab = 1 + ibase[root / VITEM] + (int)ws.wprefix[w] + __popcll(below);
-                fd->labels[v] = lab;
+                gmem(fd->labels)[v] = lab;
             }
             if (fd->min_seg > 1) {
                 // segment sizes: one atomic per distinct label of the wave
@@ -1327,8 +1353,8 @@ __global__ __launch_bounds__(NT) void k_post(const BatchHeader* __restrict__ hdr
             for (int r = 0; r < RV; ++r) {
                 const int v = v0 + r * NT + threadIdx.x;
                 if (v < V) {
-                    const int lab = fd->labels[v];
-                    if (lab > 0 && size[lab] < fd->min_seg) fd->labels[v] = 0;
+                    const int lab = gmem(fd->labels)[v];
+                    if (lab > 0 && size[lab] < fd->min_seg) gmem(fd->labels)[v] = 0;
                 }
             }
         } else {
@@ -1339,7 +1365,7 @@ __global__ __launch_bounds__(NT) void k_post(const BatchHeader* __restrict__ hdr
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
                 const int64_t p = p0 + r * NT;
-                if (p < fd->n_points) fd->point_labels[p] = backfill_label(fd, ws, ws.pcell[fd->pt_off + p]);
+                if (p < fd->n_points) gmem(fd->point_labels)[p] = backfill_label(fd, ws, ws.pcell[fd->pt_off + p]);
             }
         }
     }
