@@ -1049,11 +1049,14 @@ __device__ __forceinline__ void g_jump(int* P, int x) {
 // Union of two local roots from a border join.  The larger of the two is
 // usually still a root (the right tile's segment, not yet joined to anything):
 // then one compare-and-swap links it under the smaller, with no walk up the
-// left tile's tree.  Otherwise the general union runs.
+// left tile's tree.  Several joins across one border often pair the same two
+// segments: when the swap finds the larger already linked to the smaller, the
+// union is done as well.  Otherwise the general union runs.
 __device__ __forceinline__ void g_union_fast(int* P, int a, int b) {
     const int x = max(a, b), y = min(a, b);
     if (x == y) return;
-    if (atomicCAS(P + x, x, y) == x) return;
+    const int old = atomicCAS(P + x, x, y);
+    if (old == x || old == y) return;
     g_union(P, a, b);
 }
 
