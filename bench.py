@@ -4,10 +4,13 @@ on one MI355X, for a batch of uneven synthetic sweeps resident in HBM.
 
 One step = the full path over the batch (64 street sweeps; rings drawn from
 {16,32,64,128}, azimuth widths from {1024,2048,4096}; range noise 1 cm; 10%
-dropouts; per-frame seeds).  `value` is points/s of the batched form replayed
-from a captured hipGraph; the same batch is also timed with plain per-frame
-launch chains and with the batched chain launched directly, and the dominant
-kernel is timed with HIP events for the roofline figure.
+dropouts; per-frame seeds), as one library call.  The batch is timed in every
+launch form: the batched chain replayed from a captured hipGraph, launched
+directly, launched directly with two batches in flight (two contexts and
+streams taken in turn, each call still a whole pass over the batch), and as
+plain per-frame chains.  `value` is points/s of the fastest form that serves
+whole batches (`config.launch` names it).  The dominant kernel is timed with
+HIP events for the roofline figure.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -161,6 +164,8 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="workgroups per batched stage, 0 = library default")
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
+    ap.add_argument("--in-flight", type=int, default=2,
+                    help="also time the batched form with this many batches in flight (1 = skip)")
     ap.add_argument("--forms", default="graph,batched,plain",
                     help="launch forms to time (graph is always timed: it gives value)")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the edge-score leg")
@@ -217,20 +222,26 @@ def main():
 
     host_ms = {}
 
-    def run(launch, steps, warmup):
-        # W warmup steps, and at least half a second of this form, so clocks settle
+    def run(launch, steps, warmup, lanes=None, name=None):
+        # W warmup steps, and at least half a second of this form, so clocks settle.
+        # lanes: [(ctx, prepared call, stream), ...] used in turn, one step each, so
+        # that many batches are in flight (each with its own workspace and outputs)
+        lanes = lanes or [(ctx, prep, stream)]
+        name = name or launch
         t_w = time.perf_counter()
         n_w = 0
         while n_w < warmup or time.perf_counter() - t_w < 0.5:
-            ctx.lidar_mesh_segment(prep, stream, launch)
+            c, pr, st = lanes[n_w % len(lanes)]
+            c.lidar_mesh_segment(pr, st, launch)
             n_w += 1
             if n_w % 8 == 0:
                 torch.cuda.synchronize()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
-            ctx.lidar_mesh_segment(prep, stream, launch)
-        host_ms[launch] = (time.perf_counter() - t) * 1000.0 / steps
+        for k in range(steps):
+            c, pr, st = lanes[k % len(lanes)]
+            c.lidar_mesh_segment(pr, st, launch)
+        host_ms[name] = (time.perf_counter() - t) * 1000.0 / steps
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1000.0 / steps
 
@@ -247,6 +258,29 @@ def main():
         ms = run(form, args.steps, args.warmup)
         log(f"  {form}: {ms:.3f} ms/step (host enqueue {host_ms[form]:.3f} ms/step)")
         forms[form] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4)}
+    if args.in_flight > 1 and "batched" in args.forms.split(","):
+        # the batched form with several batches in flight: each step is still one
+        # whole call over the batch, on one of `in_flight` contexts (workspace and
+        # outputs of its own) and streams, taken in turn, so one batch's
+        # latency-bound labelling stages overlap the next batch's mesh stages
+        name = f"batched_x{args.in_flight}"
+        log(f"timing batched launches, {args.in_flight} batches in flight")
+        extra = []
+        for _ in range(args.in_flight):
+            c2 = lp.LidarContext(0)
+            c2.set_tuning(shape["grid"], shape["tile_cells"], shape["tile_threads"])
+            o2 = [lp.Outputs(g, dev) for g in geos]
+            extra.append((c2, c2.prepare(inputs, params, o2), torch.cuda.Stream(dev), o2))
+        ms = run("batched", args.steps, args.warmup, [(c2, p2, s2) for c2, p2, s2, _ in extra], name)
+        same = all(torch.equal(a.labels, b.labels) and torch.equal(a.counts, b.counts)
+                   for c2, p2, s2, o2 in extra for a, b in zip(outs, o2))
+        log(f"  {name}: {ms:.3f} ms/step (host enqueue {host_ms[name]:.3f} ms/step), outputs as one in flight: {same}")
+        if not same:
+            raise RuntimeError("batches in flight gave other outputs than one batch alone")
+        forms[name] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4)}
+        for c2, _, _, _ in extra:
+            c2.close()
+        del extra
     # roofline kernel: per-stage HIP events on the launch stream over K batched steps.
     # k_geom moves most of the path's algorithmic bytes (the kept points in; the
     # vertices, normals, vertex points and triangles out), so the roofline is its.
@@ -278,8 +312,12 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 5),
                 "stage_ms": {k: round(v, 5) for k, v in per_launch.items()}}
+    # value: the fastest form that serves whole batches (graph replay, batched
+    # launches, or batched launches with several batches in flight)
+    best = max((f for f in forms if f != "plain"), key=lambda f: forms[f]["points_per_s"])
+    ms_best = forms[best]["ms_per_step"]
     alg_path = 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T   # whole path, as in the byte model
-    path_gbs = alg_path / (ms_graph * 1e-3) / 1e9
+    path_gbs = alg_path / (ms_best * 1e-3) / 1e9
 
     accuracy = None
     if not args.no_accuracy:
@@ -308,7 +346,7 @@ def main():
                          f"host has {os.cpu_count()} CPUs"}
         log(f"  oracle: {done_pts / el:.0f} points/s")
 
-    value = N / (ms_graph * 1e-3)
+    value = N / (ms_best * 1e-3)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -316,7 +354,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_graph, 4),
+        "ms_per_step": round(ms_best, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -325,7 +363,7 @@ def main():
         "config": {"workload": f"batched {args.frames} uneven street sweeps (rings 16/32/64/128, "
                                f"azimuth 1024/2048/4096, s=1)", "frames": args.frames,
                    "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
-                   "launch": "graph", "seed": args.seed, "launch_shape": shape, "launch_shape_source": shape_src},
+                   "launch": best, "seed": args.seed, "launch_shape": shape, "launch_shape_source": shape_src},
         "forms": forms,
         "path_algorithmic_gbs": round(path_gbs, 1),
         "roofline": roofline,
