@@ -41,7 +41,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        L.oracle_bin.argtypes = [P, i64, i32, i32, i32, P, f64, f64, f64, P]
+        L.oracle_bin.argtypes = [P, P, i64, i32, i32, i32, P, f64, f64, f64, P]
         L.oracle_bin.restype = i64
         L.oracle_vertex_index.argtypes = [i32, i32, P, P]
         L.oracle_vertex_index.restype = i64
@@ -57,13 +57,13 @@ def lib():
         L.oracle_labels_pred.restype = i64
         L.oracle_prune.argtypes = [P, i64, i64, i32]
         L.oracle_prune.restype = None
-        L.oracle_point_cells.argtypes = [P, i64, i32, i32, P, f64, f64, f64, P, P]
+        L.oracle_point_cells.argtypes = [P, P, i64, i32, i32, P, f64, f64, f64, P, P]
         L.oracle_point_cells.restype = None
         L.oracle_backfill.argtypes = [i64, P, P, i32, i32, i32, i32, P, P]
         L.oracle_backfill.restype = None
         L.oracle_edge_scores.argtypes = [i32, i32, i32, P, P, i32, P]
         L.oracle_edge_scores.restype = None
-        L.oracle_mesh_segment_ex.argtypes = [P, i64, i32, i32, i32, i32, P, f64, f64, f64, i32, P, f64, i32,
+        L.oracle_mesh_segment_ex.argtypes = [P, P, i64, i32, i32, i32, i32, P, f64, f64, f64, i32, P, f64, i32,
                                              P, P, P, P, P, P, P, P]
         L.oracle_mesh_segment_ex.restype = ctypes.c_int
         L.oracle_mesh_segment.argtypes = [P, i64, i32, i32, i32, i32, P, f64, f64, f64, P,
@@ -85,13 +85,23 @@ def _c(a, dtype):
 # stage functions
 
 
-def bin_points(xyz, H, W, s, elev, az0=0.0, r_min=1.0, r_max=60.0):
-    """Steps 1-2: cell_point[k*H+i] = kept point index or -1."""
+def _rings(ring_ids, n):
+    if ring_ids is None:
+        return None, None
+    r = _c(ring_ids, np.uint8).reshape(-1)
+    assert r.shape[0] == n
+    return r, _p(r)
+
+
+def bin_points(xyz, H, W, s, elev, az0=0.0, r_min=1.0, r_max=60.0, ring_ids=None):
+    """Steps 1-2: cell_point[k*H+i] = kept point index or -1.  ring_ids: each
+    point's reported ring (uint8), or None to decide rings by elevation."""
     xyz = _c(xyz, np.float32).reshape(-1, 3)
     elev = _c(elev, np.float64)
+    rk, rp = _rings(ring_ids, xyz.shape[0])
     Wp = W // s
     out = np.empty(H * Wp, dtype=np.int64)
-    lib().oracle_bin(_p(xyz), xyz.shape[0], H, W, s, _p(elev), az0, r_min, r_max, _p(out))
+    lib().oracle_bin(_p(xyz), rp, xyz.shape[0], H, W, s, _p(elev), az0, r_min, r_max, _p(out))
     return out
 
 
@@ -140,13 +150,14 @@ def prune(vertex_labels, K, min_size):
     return out
 
 
-def point_cells(xyz, H, W, elev, az0=0.0, r_min=1.0, r_max=60.0):
+def point_cells(xyz, H, W, elev, az0=0.0, r_min=1.0, r_max=60.0, ring_ids=None):
     """Every point's full-resolution (ring, firing), -1 for a point that is not used."""
     xyz = _c(xyz, np.float32).reshape(-1, 3)
     elev = _c(elev, np.float64)
+    rk, rp = _rings(ring_ids, xyz.shape[0])
     ring = np.empty(xyz.shape[0], np.int32)
     firing = np.empty(xyz.shape[0], np.int32)
-    lib().oracle_point_cells(_p(xyz), xyz.shape[0], H, W, _p(elev), az0, r_min, r_max, _p(ring), _p(firing))
+    lib().oracle_point_cells(_p(xyz), rp, xyz.shape[0], H, W, _p(elev), az0, r_min, r_max, _p(ring), _p(firing))
     return ring, firing
 
 
@@ -212,10 +223,12 @@ class Result:
 
 
 def mesh_segment(xyz, H, W, s, elev, *, az0=0.0, r_min=1.0, r_max=60.0, thr=(0.2, 0.2, 0.2),
-                 wrap=1, predicate=0, cos_min=0.0, min_segment=0, point_labels=False) -> Result:
+                 wrap=1, predicate=0, cos_min=0.0, min_segment=0, point_labels=False, ring_ids=None) -> Result:
     """The whole path on one sweep (compact outputs in vertex order); with
-    point_labels, every input point's label as well (step 6b)."""
+    point_labels, every input point's label as well (step 6b); ring_ids: each
+    point's reported ring instead of the elevation decision."""
     xyz = _c(xyz, np.float32).reshape(-1, 3)
+    rk, rp = _rings(ring_ids, xyz.shape[0])
     elev = _c(elev, np.float64)
     thr = _c(thr, np.float64)
     Wp = W // s
@@ -228,7 +241,7 @@ def mesh_segment(xyz, H, W, s, elev, *, az0=0.0, r_min=1.0, r_max=60.0, thr=(0.2
     N64 = np.empty((cells, 3), np.float64)
     PL = np.empty(max(xyz.shape[0], 1), np.int32) if point_labels else None
     cnt = np.zeros(3, np.int64)
-    rc = lib().oracle_mesh_segment_ex(_p(xyz), xyz.shape[0], H, W, s, wrap, _p(elev), az0, r_min, r_max,
+    rc = lib().oracle_mesh_segment_ex(_p(xyz), rp, xyz.shape[0], H, W, s, wrap, _p(elev), az0, r_min, r_max,
                                       int(predicate), _p(thr), float(cos_min), int(min_segment), _p(V), _p(Nn),
                                       _p(L), _p(T), _p(VP), _p(cnt), _p(N64), _p(PL) if PL is not None else None)
     if rc != 0:

@@ -24,8 +24,9 @@
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes of the repository):
  *   - a point belongs to the ring whose elevation is nearest to atan2(z, rho)
- *     (tie: lower ring index) and to the azimuth firing round((phi - phi0)/dphi)
- *     mod W, round half away from zero;
+ *     (tie: lower ring index) -- or to the ring the sensor reported for it, when
+ *     given (a reported ring beyond the lattice: the point is not used) -- and to
+ *     the azimuth firing round((phi - phi0)/dphi) mod W, round half away from zero;
  *   - "within range" is r_min^2 <= x^2+y^2+z^2 <= r_max^2 in FP64;
  *   - two returns in one cell: the smaller float(r^2) wins, then the lower index;
  *   - "consecutive vectors" are cycle-adjacent pairs (A,B),(B,C),...,(F,A) with
@@ -82,10 +83,11 @@ static int64_t neighbour_cell(int32_t H, int32_t Wp, int32_t wrap, int32_t i, in
 /* ------------------------------------------------------------------------ */
 /* Steps 1-2: binning and sub-sampling.
  * The lattice position of one point: its ring (nearest elevation, the upper ring
- * on a tie) and firing (nearest azimuth sample, round half away from zero,
- * modulo W), both decided in FP64.  Returns 0 when the point is not used
- * (non-finite, or outside the range window), 1 otherwise; r2 receives x^2+y^2+z^2. */
-static int bin_decide(const float* q, int32_t H, int32_t W, const double* elev, double az0,
+ * on a tie -- or the ring the sensor reported, given >= 0) and firing (nearest
+ * azimuth sample, round half away from zero, modulo W), both decided in FP64.
+ * Returns 0 when the point is not used (non-finite, outside the range window,
+ * or a reported ring beyond the lattice), 1 otherwise; r2 receives x^2+y^2+z^2. */
+static int bin_decide(const float* q, int32_t given, int32_t H, int32_t W, const double* elev, double az0,
                       double rmin2, double rmax2, int32_t* ring_out, int64_t* firing_out, double* r2_out)
 {
     double x = q[0], y = q[1], z = q[2];
@@ -94,13 +96,18 @@ static int bin_decide(const float* q, int32_t H, int32_t W, const double* elev, 
     double r2 = rho2 + z * z;
     if (r2 < rmin2 || r2 > rmax2) return 0;                /* "within range of the Lidar" */
 
-    /* ring: nearest elevation, first (upper) ring on a tie */
-    double el = atan2(z, sqrt(rho2));
     int32_t ring = 0;
-    double best = fabs(el - elev[0]);
-    for (int32_t i = 1; i < H; ++i) {
-        double d = fabs(el - elev[i]);
-        if (d < best) { best = d; ring = i; }
+    if (given >= 0) {
+        if (given >= H) return 0;
+        ring = given;
+    } else {
+        /* ring: nearest elevation, first (upper) ring on a tie */
+        double el = atan2(z, sqrt(rho2));
+        double best = fabs(el - elev[0]);
+        for (int32_t i = 1; i < H; ++i) {
+            double d = fabs(el - elev[i]);
+            if (d < best) { best = d; ring = i; }
+        }
     }
 
     /* firing: nearest azimuth sample of the spin */
@@ -115,8 +122,9 @@ static int bin_decide(const float* q, int32_t H, int32_t W, const double* elev, 
     return 1;
 }
 
-/* cell_point[c] = index of the point kept in cell c, or -1.  Returns #occupied. */
-int64_t oracle_bin(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
+/* cell_point[c] = index of the point kept in cell c, or -1.  Returns #occupied.
+ * ring_ids: each point's reported ring, or NULL to decide rings by elevation. */
+int64_t oracle_bin(const float* xyz, const uint8_t* ring_ids, int64_t n, int32_t H, int32_t W, int32_t s,
                    const double* elev, double az0, double r_min, double r_max,
                    int64_t* cell_point)
 {
@@ -133,7 +141,8 @@ int64_t oracle_bin(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
         int32_t ring;
         int64_t j;
         double r2;
-        if (!bin_decide(xyz + 3 * p, H, W, elev, az0, rmin2, rmax2, &ring, &j, &r2)) continue;
+        if (!bin_decide(xyz + 3 * p, ring_ids ? ring_ids[p] : -1, H, W, elev, az0, rmin2, rmax2, &ring, &j, &r2))
+            continue;
         if (j % s != 0) continue;                           /* sub-sampling */
         int64_t c = (j / s) * H + ring;
 
@@ -150,14 +159,15 @@ int64_t oracle_bin(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
 
 /* Every point's ring and firing (full resolution, before sub-sampling), or
  * ring = firing = -1 for a point that is not used. */
-void oracle_point_cells(const float* xyz, int64_t n, int32_t H, int32_t W, const double* elev,
-                        double az0, double r_min, double r_max, int32_t* ring, int32_t* firing)
+void oracle_point_cells(const float* xyz, const uint8_t* ring_ids, int64_t n, int32_t H, int32_t W,
+                        const double* elev, double az0, double r_min, double r_max, int32_t* ring, int32_t* firing)
 {
     for (int64_t p = 0; p < n; ++p) {
         int32_t i;
         int64_t j;
         double r2;
-        if (bin_decide(xyz + 3 * p, H, W, elev, az0, r_min * r_min, r_max * r_max, &i, &j, &r2)) {
+        if (bin_decide(xyz + 3 * p, ring_ids ? ring_ids[p] : -1, H, W, elev, az0, r_min * r_min, r_max * r_max, &i,
+                       &j, &r2)) {
             ring[p] = i;
             firing[p] = (int32_t)j;
         } else {
@@ -407,7 +417,7 @@ void oracle_backfill(int64_t n, const int32_t* ring, const int32_t* firing, int3
  * the cosine test); min_segment > 1 removes smaller segments (step 6a).
  * Capacity: V <= H*(W/s), T <= 2*H*(W/s).  normals64 (optional, [V][3]) receives
  * the unrounded FP64 normals.  Returns 0, or -1 on a bad argument. */
-int oracle_mesh_segment_ex(const float* xyz, int64_t n, int32_t H, int32_t W, int32_t s,
+int oracle_mesh_segment_ex(const float* xyz, const uint8_t* ring_ids, int64_t n, int32_t H, int32_t W, int32_t s,
                            int32_t wrap, const double* elev, double az0, double r_min,
                            double r_max, int32_t pred, const double* thr, double cos_min,
                            int32_t min_segment, float* vertices, float* normals, int32_t* labels,
@@ -426,7 +436,7 @@ int oracle_mesh_segment_ex(const float* xyz, int64_t n, int32_t H, int32_t W, in
     float* n32 = (float*)malloc(sizeof(float) * 3 * (size_t)ncell);
     int32_t* lab = (int32_t*)malloc(sizeof(int32_t) * (size_t)ncell);
 
-    oracle_bin(xyz, n, H, W, s, elev, az0, r_min, r_max, cell_point);
+    oracle_bin(xyz, ring_ids, n, H, W, s, elev, az0, r_min, r_max, cell_point);
     for (int64_t c = 0; c < ncell; ++c) {
         valid[c] = cell_point[c] >= 0;
         for (int d = 0; d < 3; ++d)
@@ -456,7 +466,7 @@ int oracle_mesh_segment_ex(const float* xyz, int64_t n, int32_t H, int32_t W, in
         for (int64_t c = 0; c < ncell; ++c) lab[c] = valid[c] ? labels[v++] : -1;
         int32_t* pr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
         int32_t* pf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-        oracle_point_cells(xyz, n, H, W, elev, az0, r_min, r_max, pr, pf);
+        oracle_point_cells(xyz, ring_ids, n, H, W, elev, az0, r_min, r_max, pr, pf);
         oracle_backfill(n, pr, pf, H, W, s, wrap, lab, point_labels);
         free(pr); free(pf);
     }
@@ -473,7 +483,7 @@ int oracle_mesh_segment(const float* xyz, int64_t n, int32_t H, int32_t W, int32
                         int32_t* labels, int32_t* triangles, int32_t* vertex_point,
                         int64_t* counts, double* normals64)
 {
-    return oracle_mesh_segment_ex(xyz, n, H, W, s, wrap, elev, az0, r_min, r_max, 0, thr, 0.0, 0,
+    return oracle_mesh_segment_ex(xyz, NULL, n, H, W, s, wrap, elev, az0, r_min, r_max, 0, thr, 0.0, 0,
                                   vertices, normals, labels, triangles, vertex_point, counts, normals64,
                                   NULL);
 }

@@ -115,3 +115,48 @@ def test_ring_tie_goes_to_the_upper_ring():
     xyz = np.array([[10.0, 0.0, 0.0]], dtype=np.float32)
     cp = oracle.bin_points(xyz, 2, 8, 1, np.array([a, -a]))
     assert np.nonzero(cp >= 0)[0].tolist() == [0]
+
+
+# ---------------------------------------------------------------- reported rings
+
+def test_reported_rings_equal_to_the_generating_ones_change_nothing():
+    f = synth.workload_frames("c2_64x2048")[0]
+    sen = f.sensor
+    by_elev = oracle.bin_points(f.xyz, sen.n_rings, sen.n_azimuth, 2, sen.elevations(), r_min=0.5, r_max=500.0)
+    given = oracle.bin_points(f.xyz, sen.n_rings, sen.n_azimuth, 2, sen.elevations(), r_min=0.5, r_max=500.0,
+                              ring_ids=f.ring.astype(np.uint8))
+    assert np.array_equal(given, by_elev)
+
+
+def test_reported_rings_decide_the_ring_alone():
+    """A relabelled ring map moves every point to its reported ring (in its own
+    firing), whatever the elevation table says; a ring beyond the lattice drops
+    the point."""
+    f = synth.workload_frames("c1_16x1800")[0]
+    sen = f.sensor
+    H, W = sen.n_rings, sen.n_azimuth
+    rng = np.random.Generator(np.random.PCG64(5))
+    perm = rng.permutation(H)
+    reported = perm[f.ring].astype(np.uint8)
+    out_of_range = rng.random(f.n_points) < 0.05
+    reported[out_of_range] = H + 3
+    # a different (still descending) elevation table must not matter
+    fake_elev = np.linspace(0.5, -0.5, H)
+    cp = oracle.bin_points(f.xyz, H, W, 1, fake_elev, r_min=0.5, r_max=500.0, ring_ids=reported)
+    exp = np.full(H * W, -1, dtype=np.int64)
+    keep = ~out_of_range
+    exp[f.col[keep] * H + reported[keep]] = np.nonzero(keep)[0]
+    assert np.array_equal(cp, exp)
+    ring, firing = oracle.point_cells(f.xyz, H, W, fake_elev, r_min=0.5, r_max=500.0, ring_ids=reported)
+    assert np.array_equal(ring[keep], reported[keep].astype(np.int32))
+    assert np.array_equal(firing[keep], f.col[keep])
+    assert np.all(ring[out_of_range] == -1)
+
+
+def test_reported_rings_through_the_whole_path():
+    f = synth.workload_frames("paper_32x1800")[0]
+    sen = f.sensor
+    a = oracle.mesh_segment_frame(f, s=5)
+    b = oracle.mesh_segment_frame(f, s=5, ring_ids=f.ring.astype(np.uint8))
+    assert np.array_equal(a.vertices, b.vertices) and np.array_equal(a.labels, b.labels)
+    assert np.array_equal(a.triangles, b.triangles)
