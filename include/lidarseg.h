@@ -23,7 +23,8 @@
  *   - Ring i = 0 is the topmost laser, counting downwards; elevations are given
  *     strictly descending.  Azimuth phi = atan2(y, x) (anticlockwise about +z);
  *     firing j has phi_j = az0 + j * 2*pi / W.  A point belongs to the ring of
- *     nearest elevation (tie: lower i) and to firing round((phi - az0)/dphi) mod W
+ *     nearest elevation (tie: lower i), or to the ring the sensor reported for it
+ *     (lidar_frame_t.ring_ids), and to firing round((phi - az0)/dphi) mod W
  *     (round half away from zero); both decided in FP64.
  *   - Sub-sampling keeps firings j = 0 (mod s); sampled column k = j / s, W' = W / s.
  *   - A point is used iff its coordinates are finite and
@@ -80,6 +81,10 @@ typedef struct {
     const int32_t* truth_ids;      /* device [n_points] or NULL: ground-truth surface id
                                       of every input point, read only for the edge
                                       scores (lidar_result_t.edge_counts) */
+    const uint8_t* ring_ids;       /* device [n_points] or NULL: the ring (laser) each
+                                      point was fired by, as the sensor reports it; it
+                                      replaces the nearest-elevation decision, and a
+                                      point whose ring is >= n_rings is not used */
 } lidar_frame_t;
 
 /* Similarity tests of lidar_params_t.predicate. */

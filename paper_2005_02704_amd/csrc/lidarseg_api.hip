@@ -530,6 +530,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         d.pt_off = pt_off;
         d.point_labels = r.point_labels;
         d.truth = r.edge_counts ? fr.truth_ids : nullptr;
+        d.rings = fr.ring_ids;
         d.scores = r.edge_counts;
         d.score_r = params->score_radius;
         d.pred = params->predicate;

@@ -30,6 +30,7 @@ struct FrameDesc {
     int64_t* counts;
     int32_t* point_labels;    // may be null: every input point's label
     const int32_t* truth;     // may be null: ground-truth surface id per input point
+    const uint8_t* rings;     // may be null: the reported ring of each input point
     int64_t* scores;          // may be null: the frame's edge counts (needs truth)
     int64_t n_points;
     int64_t cell_off;         // first cell of this frame in the key grid and the forest

@@ -248,6 +248,7 @@ __global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ h
             }
         }
         int32_t* const pcell = fd->point_labels ? ws.pcell + fd->pt_off : nullptr;
+        const auto rings = gmem(fd->rings);   // the sensor's own ring of each point, if given
         // fast pass: FP32 estimates; a point inside a guard band is only flagged
         uint32_t hard = 0;
 #pragma unroll
@@ -259,15 +260,18 @@ __global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ h
             const double rho2 = x * x + y * y;   // products of floats are exact in FP64
             const double r2 = rho2 + z * z;
             used = used && r2 >= rmin2 && r2 <= rmax2;
+            const int given = (used && rings) ? (int)rings[p] : -1;
+            used = used && given < H;
             if (!used) {
                 if (pcell && p < np) pcell[p] = -1;
                 continue;
             }
-            // ring: t against the midpoint tangents, through the bucket table
+            // ring: the reported one, or t against the midpoint tangents, through
+            // the bucket table
             const float t = zf * __builtin_amdgcn_rsqf(fmaf(xf, xf, yf * yf));
-            int ring = 0;
-            bool exact = !isfinite(t);
-            if (!exact) {
+            int ring = given;
+            bool exact = given < 0 && !isfinite(t);
+            if (given < 0 && !exact) {
                 const float bf = fminf(fmaxf((t - lo) * inv, 0.0f), (float)(RING_LUT - 1));
                 ring = s_lut[(int)bf];
                 for (int k = 0; k < MAX_RINGS && ring > 0 && t > s_T[ring - 1]; ++k) --ring;
@@ -292,7 +296,8 @@ __global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ h
                 const double x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
                 const double rho2 = x * x + y * y;
                 const double r2 = rho2 + z * z;
-                bin_store(keys, pcell, p, ring_fp64(s_elev, H, z, rho2), firing_fp64(x, y, az0, dphi), W, H, s, r2);
+                const int ring = rings ? (int)rings[p] : ring_fp64(s_elev, H, z, rho2);
+                bin_store(keys, pcell, p, ring, firing_fp64(x, y, az0, dphi), W, H, s, r2);
             }
         }
     }

@@ -51,7 +51,8 @@ class lidar_sensor_t(ctypes.Structure):
 
 class lidar_frame_t(ctypes.Structure):
     _fields_ = [("sensor", ctypes.POINTER(lidar_sensor_t)), ("xyz", ctypes.c_void_p),
-                ("n_points", ctypes.c_int64), ("normals_in", ctypes.c_void_p), ("truth_ids", ctypes.c_void_p)]
+                ("n_points", ctypes.c_int64), ("normals_in", ctypes.c_void_p), ("truth_ids", ctypes.c_void_p),
+                ("ring_ids", ctypes.c_void_p)]
 
 
 class lidar_params_t(ctypes.Structure):
@@ -231,12 +232,14 @@ class LidarContext:
         for f, item in enumerate(inputs):
             xyz, sensor, normals_in = item[:3]
             truth = item[3] if len(item) > 3 else None
+            rings = item[4] if len(item) > 4 else None
             sc = sensor.c_struct()
             keep.append(sc)
             frames[f] = lidar_frame_t(ctypes.pointer(sc), xyz.data_ptr() if xyz.numel() else None,
                                       int(xyz.shape[0]),
                                       normals_in.data_ptr() if normals_in is not None else None,
-                                      truth.data_ptr() if truth is not None and truth.numel() else None)
+                                      truth.data_ptr() if truth is not None and truth.numel() else None,
+                                      rings.data_ptr() if rings is not None and rings.numel() else None)
             results[f] = outputs[f].c_struct()
         return (frames, n, params, results, keep)
 
@@ -272,7 +275,8 @@ def lidar_mesh_segment(ctx: LidarContext, inputs, params: lidar_params_t | None 
                        launch: str = "batched", stream=None, with_vertex_point=True, point_labels=False,
                        scores=False):
     """Convenience: inputs = [(xyz cuda float32 [N,3], SensorGeometry, normals_in or None
-    [, truth ids cuda int32 [N]])]; scores asks for the edge counts (needs truth ids).
+    [, truth ids cuda int32 [N] or None [, reported rings cuda uint8 [N]]])]; scores asks
+    for the edge counts (needs truth ids).
 
     Allocates outputs, enqueues the call and returns the Outputs objects (call
     .trimmed() to synchronise and cut them to their counts)."""

@@ -18,7 +18,8 @@ def geometry(sensor, s=1, wrap=1):
 def run_gpu(ctx, items, launch="plain", r_min=1.0, r_max=60.0, thr=THR, predicate=0, cos_min=0.0, min_segment=0,
             point_labels=False, score_radius=None):
     """items: list of (xyz float32 [N,3] numpy, synth.Sensor, s, wrap, normals_in or None
-    [, truth ids int32 [N]]); score_radius (with truth ids) asks for the edge counts."""
+    [, truth ids int32 [N] or None [, reported rings uint8 [N]]]); score_radius (with
+    truth ids) asks for the edge counts."""
     import torch
     import paper_2005_02704_amd as lp
     inputs = []
@@ -26,8 +27,10 @@ def run_gpu(ctx, items, launch="plain", r_min=1.0, r_max=60.0, thr=THR, predicat
         xyz, sen, s, wrap, nin = it[:5]
         x = torch.from_numpy(np.ascontiguousarray(xyz, np.float32)).cuda()
         n = torch.from_numpy(np.ascontiguousarray(nin, np.float32)).cuda() if nin is not None else None
-        tr = torch.from_numpy(np.ascontiguousarray(it[5], np.int32)).cuda() if len(it) > 5 else None
-        inputs.append((x, geometry(sen, s, wrap), n, tr))
+        tr = torch.from_numpy(np.ascontiguousarray(it[5], np.int32)).cuda() if len(it) > 5 and it[5] is not None \
+            else None
+        rg = torch.from_numpy(np.ascontiguousarray(it[6], np.uint8)).cuda() if len(it) > 6 else None
+        inputs.append((x, geometry(sen, s, wrap), n, tr, rg))
     params = lp.make_params(r_min, r_max, thr, predicate, cos_min, min_segment,
                             score_radius if score_radius is not None else 1)
     outs = lp.lidar_mesh_segment(ctx, inputs, params, launch=launch, point_labels=point_labels,

@@ -112,3 +112,26 @@ def test_repeat_runs_bitwise(ctx):
         b = run_gpu(ctx, [(f.xyz, f.sensor, 2, 1, None)], launch="batched")[0]
         for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
             assert np.array_equal(a[k], b[k])
+
+
+def test_reported_rings(ctx):
+    """Rings the sensor reports replace the elevation decision: equal to the
+    generating rings they change nothing; relabelled (and some out of range)
+    they move the points exactly as in the oracle."""
+    f = synth.workload_frames("c2_64x2048")[0]
+    sen = f.sensor
+    H = sen.n_rings
+    plain = run_gpu(ctx, [(f.xyz, sen, 2, 1, None)], launch="batched")[0]
+    same = run_gpu(ctx, [(f.xyz, sen, 2, 1, None, None, f.ring.astype(np.uint8))], launch="batched")[0]
+    for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
+        assert np.array_equal(plain[k], same[k]), k
+    rng = np.random.Generator(np.random.PCG64(9))
+    reported = rng.permutation(H)[f.ring].astype(np.uint8)
+    reported[rng.random(f.n_points) < 0.03] = 200
+    r = run_oracle(f.xyz, sen, 2, ring_ids=reported, point_labels=True)
+    for launch in ("plain", "graph"):
+        g = run_gpu(ctx, [(f.xyz, sen, 2, 1, None, None, reported)], launch=launch, point_labels=True)[0]
+        check_geometry(g, r)
+        g2 = run_gpu(ctx, [(f.xyz, sen, 2, 1, r.normals, None, reported)], launch=launch, point_labels=True)[0]
+        assert np.array_equal(g2["labels"], r.labels)
+        assert np.array_equal(g2["point_labels"], r.point_labels)
