@@ -135,3 +135,52 @@ def test_reported_rings(ctx):
         g2 = run_gpu(ctx, [(f.xyz, sen, 2, 1, r.normals, None, reported)], launch=launch, point_labels=True)[0]
         assert np.array_equal(g2["labels"], r.labels)
         assert np.array_equal(g2["point_labels"], r.point_labels)
+
+
+def test_call_arguments_are_rejected_before_any_work(ctx):
+    """Every bad argument of lidar_mesh_segment returns LIDAR_EINVAL with a
+    message, and the context stays usable."""
+    import ctypes
+    import torch
+    import paper_2005_02704_amd as lp
+    from paper_2005_02704_amd import lidarseg as b
+    from gpu_helpers import geometry
+    f = synth.workload_frames("c1_16x1800")[0]
+    geo = geometry(f.sensor)
+    x = torch.from_numpy(f.xyz).cuda()
+    dev = torch.device("cuda", 0)
+
+    def call(params=None, launch="batched", outs=None, inputs=None):
+        o = outs or [lp.Outputs(geo, dev)]
+        prep = ctx.prepare(inputs or [(x, geo, None)], params or lp.make_params(), o)
+        ctx.lidar_mesh_segment(prep, launch=launch)
+
+    bad_params = [lp.make_params(r_min=-1.0), lp.make_params(r_min=5.0, r_max=4.0),
+                  lp.make_params(r_max=float("inf")), lp.make_params(thr=(0.2, 0.0, 0.2)),
+                  lp.make_params(thr=(0.2, 0.2, float("nan"))), lp.make_params(predicate=7),
+                  lp.make_params(predicate=lp.LIDAR_PRED_COSINE, cos_min=1.0), lp.make_params(min_segment=-2)]
+    for p in bad_params:
+        with pytest.raises(lp.LidarError) as e:
+            call(params=p)
+        assert e.value.code == lp.LIDAR_EINVAL and str(e.value)
+    with pytest.raises(lp.LidarError):
+        call(launch=9)
+    # a required output missing
+    o = lp.Outputs(geo, dev)
+    prep = ctx.prepare([(x, geo, None)], lp.make_params(), [o])
+    prep[3][0].labels = None
+    with pytest.raises(lp.LidarError):
+        ctx.lidar_mesh_segment(prep)
+    # points given without coordinates
+    prep = ctx.prepare([(x, geo, None)], lp.make_params(), [lp.Outputs(geo, dev)])
+    prep[0][0].xyz = None
+    with pytest.raises(lp.LidarError):
+        ctx.lidar_mesh_segment(prep)
+    # a sensor the library refuses (elevations ascending)
+    bad_geo = lp.SensorGeometry(f.sensor.elevations()[::-1].copy(), f.sensor.n_azimuth, 1)
+    with pytest.raises(lp.LidarError):
+        call(inputs=[(x, bad_geo, None)], outs=[lp.Outputs(geo, dev)])
+    # and the context still works
+    g = run_gpu(ctx, [(f.xyz, f.sensor, 1, 1, None)], launch="batched")[0]
+    r = run_oracle(f.xyz, f.sensor, 1)
+    check_geometry(g, r)
