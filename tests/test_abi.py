@@ -66,3 +66,21 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got[f"{name} size"]) == ctypes.sizeof(st), name
         for fname, _ in st._fields_:
             assert int(got[f"{name} {fname}"]) == getattr(st, fname).offset, (name, fname)
+
+
+def test_binding_refuses_to_run_without_the_library(tmp_path):
+    """The product path has no fallback: without the built library, creating a
+    context raises instead of computing anything elsewhere."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2005_02704_amd.lidarseg as L\n"
+            "try:\n"
+            "    L.load_library(%r)\n"
+            "except ImportError as e:\n"
+            "    print('refused:', e)\n"
+            "    raise SystemExit(0)\n"
+            "raise SystemExit(1)\n") % (ROOT, str(tmp_path / "missing.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "refused" in r.stdout

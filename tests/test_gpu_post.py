@@ -86,3 +86,19 @@ def test_post_stage_in_every_launch_form(ctx):
     ref0 = [run_oracle(f.xyz, f.sensor, 1) for f in frames]
     for r, g in zip(ref0, got):
         assert np.array_equal(g["labels"], r.labels)
+
+
+def test_cosine_and_removal_in_batched_and_graph_forms(ctx):
+    """The cosine test, segment removal and point labels on a batch of uneven
+    sweeps in the batched and graph forms (labels on the oracle's normals, so
+    bit-exact), replayed twice."""
+    frames = synth.batch_frames(6, 4242)
+    refs = [run_oracle(f.xyz, f.sensor, 1, predicate=1, cos_min=COS, min_segment=3, point_labels=True)
+            for f in frames]
+    items = [(f.xyz, f.sensor, 1, 1, r.normals) for f, r in zip(frames, refs)]
+    for launch in ("batched", "graph", "graph"):
+        got = run_gpu(ctx, items, launch=launch, predicate=1, cos_min=COS, min_segment=3, point_labels=True)
+        for k, (g, r) in enumerate(zip(got, refs)):
+            assert g["counts"][2] == r.counts[2], (launch, k)
+            assert np.array_equal(g["labels"], r.labels), (launch, k)
+            assert np.array_equal(g["point_labels"], r.point_labels), (launch, k)
