@@ -77,7 +77,7 @@ def served_run(args, lp, synth, torch):
         return Request(rid, s, pinned[s][k], pool[s][k].n_points, t)
 
     budget = 1 << 30
-    ex = GpuExecutor(geos, n_slots=3, launch="graph")
+    ex = GpuExecutor(geos, n_slots=3, launch=args.served_launch)
     # warm the slots (workspace growth, graph capture) before timing
     warm = Server(ex, budget_bytes=budget, max_batch=16)
     warm.run_schedule([(0.0, q, 0) for q in range(8)] * 3, make)
@@ -96,7 +96,7 @@ def served_run(args, lp, synth, torch):
     keep = ("requests", "points_per_s", "p50_ms", "p99_ms", "max_ms", "mean_batch", "max_slots_in_flight",
             "peak_device_bytes")
     return {"workload": "8 sensors, rings 16/32/64/128, azimuth 1024/2048/4096, 10-20 Hz Poisson, "
-                        f"{args.served_seconds:.0f}s, budget 1 GiB, 3 slots, graph launches",
+                        f"{args.served_seconds:.0f}s, budget 1 GiB, 3 slots, {args.served_launch} launches",
             **{k: (round(st[k], 3) if isinstance(st[k], float) else st[k]) for k in keep},
             "latency": "host arrival to labels/vertex_point/counts in pinned host memory",
             "capacity_points_per_s": round(stc["points_per_s"], 1),
@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--tile-cells", type=int, default=0, help="0 = autotuned table / library default")
     ap.add_argument("--tile-threads", type=int, default=0, help="0 = autotuned table / library default")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per batched stage, 0 = library default")
+    ap.add_argument("--served-launch", default="graph", choices=("graph", "batched"),
+                    help="launch form of the served run's groups")
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
     ap.add_argument("--in-flight", type=int, default=3,
