@@ -1,6 +1,7 @@
 // HIP kernels for gfx950 (MI355X): bin -> sub-sample -> mesh -> normals -> labels.
 //
-// One batch of frames runs as a chain of nine grid-stride kernels; each kernel
+// One batch of frames runs as a chain of nine grid-stride kernels (eleven when
+// point labels, segment removal or edge scores are asked for); each kernel
 // walks its work items (point blocks, lattice tiles, border slots, blocks of
 // vertex slots or frames) across every frame of the batch, reading the
 // per-frame descriptors from device memory, so the same launches (and the same

@@ -40,10 +40,16 @@ def _csv(d: str, suffix: str):
 
 
 def kernel_source_hash():
+    """Hash of the kernels' code (the same as bench.py's): comments and blank
+    space left out, so that an edit of a comment keeps the counters valid."""
+    import re
     h = hashlib.sha256()
     for name in ("lidarseg_kernels.hip", "lidarseg_internal.h"):
-        with open(os.path.join(ROOT, "paper_2005_02704_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2005_02704_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
