@@ -540,7 +540,7 @@ __device__ __forceinline__ void number_cells(int (&vid)[RN], const int* s_cnt, i
     }
 }
 
-// Mesh stage, per tile in LDS.  Columns lc = -1 .. TWe+1 of the tile (global
+// Mesh stage, per tile in LDS.  Columns lc = -1 .. TWe of the tile (global
 // column k0 + lc, wrapped on a closed cylinder) hold the kept points'
 // coordinates (NaN = empty cell) and vertex ids; LDS cell lx = (lc + 1) * H + i.
 // Own cells are lc in [0, TWe); the right column lc = TWe belongs to the next
@@ -548,10 +548,11 @@ __device__ __forceinline__ void number_cells(int (&vid)[RN], const int* s_cnt, i
 // l = lx - H runs over own cells and then the right column; thread x handles
 // l = x + r * NT in round r, so every 64-cell chunk is one wave's round.
 // Writes vertices, vertex_point, triangles and normals.
-// 5 waves per SIMD at up to 4 cells per thread
+// 6 waves per SIMD at up to 4 cells per thread (one more wave than the
+// registers of the unconstrained build allow; it hides more load latency)
 template <int NT, int MAXC>
-__global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const BatchHeader* __restrict__ hdr, Workspace ws) {
-    constexpr int XC = MAXC + 3 * MAX_RINGS;  // coordinate cells incl. halo
+__global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int XC = MAXC + 2 * MAX_RINGS;  // coordinate cells incl. halo
     constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
     constexpr int RX = (XC + NT - 1) / NT;
     constexpr int NW = NT / 64;
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
         const int lt = t - fd->tile_off;
         const int k0 = lt * fd->TW;
         const int TWe = min(fd->TW, Wp - k0);
-        const int nx = H * (TWe + 3);
+        const int nx = H * (TWe + 2);
         const int nown = H * TWe;
         const int nscan = nown + H;
         const uint64_t* keys = ws.keys + fd->cell_off;
@@ -583,6 +584,10 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
         const int i0 = (int)threadIdx.x - div_small(threadIdx.x, inv_h) * H;
         __syncthreads();  // LDS of the previous tile is free
 
+        // The loads of phases 1-3 go out at raised wave priority, so that a
+        // workgroup starting a tile gets its memory requests in flight ahead of
+        // the normal arithmetic of the other workgroups on the compute unit.
+        __builtin_amdgcn_s_setprio(3);
         // 1. keys of the tile and its halo columns (lx = tid + r * NT)
         uint64_t key[RX];
         {
@@ -647,6 +652,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
         }
         __syncthreads();
 
+        __builtin_amdgcn_s_setprio(0);
         // 4. numbering in firing order (own cells, then the right column)
         int vid[RN], ltr[RN];
         {
@@ -777,7 +783,8 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 5 : 1)) void k_geom(const Bat
 // local root in the forest.  sn[l] = (normal, vertex id) for l over own cells
 // and the right column, NaN components for a vertex without a normal or an
 // empty cell.
-// 6 waves per SIMD fit at up to 4 cells per thread without spilling
+// 6 waves per SIMD at up to 4 cells per thread (at 4, a few registers spill;
+// 5 waves without the spill ran slower)
 template <int NT, int MAXC>
 __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int NC = MAXC + MAX_RINGS;      // own cells + right column
