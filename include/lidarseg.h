@@ -46,7 +46,8 @@ extern "C" {
 
 #define LIDAR_OK 0
 #define LIDAR_EINVAL (-1)   /* bad argument; nothing was enqueued */
-#define LIDAR_ENOMEM (-2)   /* device workspace could not be allocated */
+#define LIDAR_ENOMEM (-2)   /* device workspace could not be allocated, or would exceed the
+                               context's limit (lidar_ctx_set_workspace_limit) */
 #define LIDAR_EDEVICE (-3)  /* a HIP runtime call failed */
 
 #define LIDAR_MAX_RINGS 128
@@ -163,6 +164,35 @@ int lidar_mesh_segment(lidar_ctx* ctx, const lidar_frame_t* frames, int32_t n_fr
                        const lidar_params_t* params, lidar_result_t* results,
                        void* stream, int32_t launch);
 
+/* Section 2 up to Normal Estimation only (binning, sub-sampling, mesh, normals):
+ * the same kernels as lidar_mesh_segment without the labelling stages, for
+ * callers (and tests) that want the mesh and its normals alone.  Arguments as
+ * for lidar_mesh_segment, except: only r_min and r_max of params are read;
+ * results[f].labels may be NULL and is not written; counts[2] (K) is written
+ * as 0; frames[f].normals_in, results[f].point_labels and results[f].edge_counts
+ * must be NULL (LIDAR_EINVAL otherwise). */
+int lidar_mesh_normals(lidar_ctx* ctx, const lidar_frame_t* frames, int32_t n_frames,
+                       const lidar_params_t* params, lidar_result_t* results,
+                       void* stream, int32_t launch);
+
+/* Algorithm 1 on normals the caller gives (the labelling stages on the
+ * lattice and mesh of each sweep): lidar_mesh_segment with
+ * frames[f].normals_in required for every frame that has points (LIDAR_EINVAL
+ * otherwise).  The given normals are copied to results[f].normals. */
+int lidar_label_grid(lidar_ctx* ctx, const lidar_frame_t* frames, int32_t n_frames,
+                     const lidar_params_t* params, lidar_result_t* results,
+                     void* stream, int32_t launch);
+
+/* Device workspace.  A context grows its workspace when a call needs more
+ * (by half as much again as asked for, to reallocate rarely) and keeps it until
+ * it is destroyed.  With a limit set (max_bytes > 0; 0 = none), a call whose
+ * batch would take the workspace above it returns LIDAR_ENOMEM before anything
+ * is enqueued (the growth slack is dropped first); memory already held is not
+ * released by a lower limit.  lidar_ctx_workspace_bytes writes the device
+ * bytes the context holds now (pinned host staging not included). */
+int lidar_ctx_set_workspace_limit(lidar_ctx* ctx, uint64_t max_bytes);
+int lidar_ctx_workspace_bytes(const lidar_ctx* ctx, uint64_t* held_bytes);
+
 /* Launch shape of every later call on this context: workgroups per grid-stride
  * stage (0 = automatic: 4 per compute unit), the largest tile in lattice cells
  * and the threads of a tile workgroup.  Supported tile shapes (cells, threads):
@@ -177,8 +207,9 @@ int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_c
  * segments), merge (segments across tiles), compress (pointer jumping on the
  * merged segments), flatten (segment roots), scan (rank bases of the roots),
  * label, post (segment removal and point labels; zero time when neither is
- * asked for), score (edge scores; zero time unless asked for).  Enabling costs
- * one event per kernel. */
+ * asked for), score (edge scores; zero time unless asked for).  In
+ * lidar_mesh_normals calls the labelling stages take zero time and flatten is
+ * the reset of the key grid.  Enabling costs one event per kernel. */
 #define LIDAR_N_STAGES 11
 int lidar_ctx_set_profiling(lidar_ctx* ctx, int32_t enable);
 /* Waits for the profiled calls, then writes the summed milliseconds and the

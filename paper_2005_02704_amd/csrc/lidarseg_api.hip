@@ -67,6 +67,22 @@ struct lidar_ctx {
     int graph_grid = 0;
     bool graph_post = false;
     bool graph_score = false;
+    bool graph_mesh_only = false;
+
+    uint64_t ws_limit = 0;        // device workspace bytes the context may hold (0 = no limit)
+
+    // Device bytes of the workspace at the given capacities.
+    static uint64_t ws_bytes(int64_t keys_n, int64_t tiles_n, int64_t vitems_n, int64_t pcell_n, int64_t aux_n,
+                             int64_t border_n, size_t table_n) {
+        return (uint64_t)keys_n * (sizeof(uint64_t) + sizeof(int32_t)) +
+               (uint64_t)tiles_n * (2 * sizeof(int32_t) + OCC_WORDS * sizeof(uint64_t)) +
+               (uint64_t)vitems_n * (VITEM_WORDS * (sizeof(uint64_t) + sizeof(uint32_t)) + sizeof(int32_t)) +
+               (uint64_t)pcell_n * sizeof(int32_t) +
+               (uint64_t)aux_n * 3 * sizeof(int32_t) + (uint64_t)border_n * sizeof(int2) + (uint64_t)table_n;
+    }
+    uint64_t held_bytes() const {
+        return ws_bytes(keys_cap, tiles_cap, vitems_cap, pcell_cap, aux_cells_cap, border_cap, table_cap);
+    }
 
     // tuning
     int grid_wg = 0;      // 0 = automatic
@@ -257,6 +273,18 @@ int lidar_ctx_set_tuning(lidar_ctx* c, int32_t grid_workgroups, int32_t tile_cel
     return LIDAR_OK;
 }
 
+int lidar_ctx_set_workspace_limit(lidar_ctx* c, uint64_t max_bytes) {
+    if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
+    c->ws_limit = max_bytes;
+    return LIDAR_OK;
+}
+
+int lidar_ctx_workspace_bytes(const lidar_ctx* c, uint64_t* held_bytes) {
+    if (!c || !held_bytes) { g_last_error = "ctx or held_bytes is NULL"; return LIDAR_EINVAL; }
+    *held_bytes = c->held_bytes();
+    return LIDAR_OK;
+}
+
 int lidar_ctx_set_profiling(lidar_ctx* c, int32_t enable) {
     if (!c) return LIDAR_EINVAL;
     c->profiling = enable != 0;
@@ -287,10 +315,16 @@ int lidar_ctx_stage_times(lidar_ctx* c, double* total_ms, int64_t* launches) {
     return LIDAR_OK;
 }
 
-int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
-                       const lidar_params_t* params, lidar_result_t* results, void* stream_,
-                       int32_t launch) {
+}  // extern "C"
+
+namespace {
+
+enum CallMode { CALL_SEGMENT = 0, CALL_MESH_ONLY = 1, CALL_LABEL_GRID = 2 };
+
+int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const lidar_params_t* params,
+              lidar_result_t* results, void* stream_, int32_t launch, CallMode mode) {
     if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
+    const bool mesh_only = mode == CALL_MESH_ONLY;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     if (n_frames < 1 || !frames || !results) return c->fail(LIDAR_EINVAL, "need n_frames >= 1 frames and results");
     if (!params) return c->fail(LIDAR_EINVAL, "params is NULL");
@@ -299,15 +333,17 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     const double rmin = params->r_min, rmax = params->r_max;
     if (!(std::isfinite(rmin) && std::isfinite(rmax) && rmin >= 0.0 && rmin <= rmax))
         return c->fail(LIDAR_EINVAL, "need finite 0 <= r_min <= r_max");
-    for (int q = 0; q < 3; ++q)
-        if (!(std::isfinite(params->thr[q]) && params->thr[q] > 0.0))
-            return c->fail(LIDAR_EINVAL, "thresholds must be finite and > 0");
-    if (params->predicate != LIDAR_PRED_COMPONENTS && params->predicate != LIDAR_PRED_COSINE)
-        return c->fail(LIDAR_EINVAL, "unknown predicate");
-    if (params->predicate == LIDAR_PRED_COSINE && !(std::isfinite(params->cos_min) && params->cos_min >= -1.0 &&
-                                                     params->cos_min < 1.0))
-        return c->fail(LIDAR_EINVAL, "cos_min must lie in [-1, 1)");
-    if (params->min_segment < 0) return c->fail(LIDAR_EINVAL, "min_segment must be >= 0");
+    if (!mesh_only) {  // the similarity test and segment floor matter only to the labelling stages
+        for (int q = 0; q < 3; ++q)
+            if (!(std::isfinite(params->thr[q]) && params->thr[q] > 0.0))
+                return c->fail(LIDAR_EINVAL, "thresholds must be finite and > 0");
+        if (params->predicate != LIDAR_PRED_COMPONENTS && params->predicate != LIDAR_PRED_COSINE)
+            return c->fail(LIDAR_EINVAL, "unknown predicate");
+        if (params->predicate == LIDAR_PRED_COSINE &&
+            !(std::isfinite(params->cos_min) && params->cos_min >= -1.0 && params->cos_min < 1.0))
+            return c->fail(LIDAR_EINVAL, "cos_min must lie in [-1, 1)");
+        if (params->min_segment < 0) return c->fail(LIDAR_EINVAL, "min_segment must be >= 0");
+    }
 
     // ---- plan ----
     std::vector<FramePlan> plan(n_frames);
@@ -320,6 +356,12 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         std::string msg;
         int rc = validate_sensor(fr.sensor, msg);
         if (rc) return c->fail(rc, "frame " + std::to_string(f) + ": " + msg);
+        if (mesh_only && (fr.normals_in || results[f].point_labels || results[f].edge_counts))
+            return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) +
+                                             ": lidar_mesh_normals estimates normals and labels nothing "
+                                             "(normals_in, point_labels and edge_counts must be NULL)");
+        if (mode == CALL_LABEL_GRID && fr.n_points > 0 && !fr.normals_in)
+            return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": lidar_label_grid needs normals_in");
         if (fr.n_points < 0 || fr.n_points > INT32_MAX)
             return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": n_points out of range");
         if (results[f].point_labels) {
@@ -340,7 +382,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             any_score = true;
         }
         const lidar_result_t& r = results[f];
-        if (!r.vertices || !r.normals || !r.labels || !r.triangles || !r.counts)
+        if (!r.vertices || !r.normals || (!r.labels && !mesh_only) || !r.triangles || !r.counts)
             return c->fail(LIDAR_EINVAL, "result " + std::to_string(f) + ": a required output is NULL");
         FramePlan& p = plan[f];
         p.H = fr.sensor->n_rings;
@@ -368,7 +410,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     }
     if (tiles > INT32_MAX || pblk > INT32_MAX || cells > MAX_BATCH_CELLS || border_slots > INT32_MAX)
         return c->fail(LIDAR_EINVAL, "batch too large (at most 2^31 - 1024 lattice cells in one call)");
-    const bool prune = params->min_segment > 1;
+    const bool prune = !mesh_only && params->min_segment > 1;
     const bool post = prune || any_point_labels;
     // plain launches run the frames one after another on shared workspace offsets
     if (launch == LIDAR_LAUNCH_PLAIN) {
@@ -399,6 +441,32 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                       border_slots > c->border_cap || table_bytes > c->table_cap ||
                       (any_point_labels && labelled_points > c->pcell_cap) ||
                       ((any_point_labels || prune || any_score) && cells > c->aux_cells_cap);
+    // new capacities: half as much again as asked for, so that a slowly
+    // growing stream of batches reallocates rarely, unless that slack would
+    // break the context's workspace limit
+    const bool aux_needed = any_point_labels || prune || any_score;
+    int64_t n_keys = c->keys_cap, n_tiles = c->tiles_cap, n_vitems = c->vitems_cap, n_pcell = c->pcell_cap,
+            n_aux = c->aux_cells_cap, n_border = c->border_cap;
+    size_t n_table = c->table_cap;
+    for (int exact = 0; grow && exact < 2; ++exact) {
+        auto cap = [&](int64_t need, int64_t have) {
+            return need <= have ? have : exact ? need : std::max<int64_t>(need, have * 3 / 2);
+        };
+        n_keys = cap(cells, c->keys_cap);
+        n_tiles = cap(tiles, c->tiles_cap);
+        n_vitems = cap(vitems, c->vitems_cap);
+        n_pcell = any_point_labels ? cap(labelled_points, c->pcell_cap) : c->pcell_cap;
+        n_aux = aux_needed ? cap(cells, c->aux_cells_cap) : c->aux_cells_cap;
+        n_border = cap(border_slots, c->border_cap);
+        n_table = table_bytes <= c->table_cap ? c->table_cap
+                  : align_up(exact ? table_bytes : std::max(table_bytes, c->table_cap * 3 / 2), 4096);
+        const uint64_t want = lidar_ctx::ws_bytes(n_keys, n_tiles, n_vitems, n_pcell, n_aux, n_border, n_table);
+        if (!c->ws_limit || want <= c->ws_limit) break;
+        if (exact)
+            return c->fail(LIDAR_ENOMEM, "the batch needs " + std::to_string(want) +
+                                             " bytes of device workspace, above the context's limit of " +
+                                             std::to_string(c->ws_limit));
+    }
     if (grow) {
         int rc = c->wait_idle();
         if (rc) return rc;
@@ -409,7 +477,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             if (c->forest) (void)hipFree(c->forest);
             c->keys = nullptr;
             c->forest = nullptr;
-            const int64_t cap = std::max<int64_t>(cells, c->keys_cap * 3 / 2);
+            const int64_t cap = n_keys;
             if (hipMalloc(&c->keys, sizeof(uint64_t) * cap) != hipSuccess ||
                 hipMalloc(&c->forest, sizeof(int32_t) * cap) != hipSuccess) {
                 c->keys_cap = 0;
@@ -425,7 +493,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             if (c->occ) (void)hipFree(c->occ);
             c->tile_buf = nullptr;
             c->occ = nullptr;
-            const int64_t cap = std::max<int64_t>(tiles, c->tiles_cap * 3 / 2);
+            const int64_t cap = n_tiles;
             if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess ||
                 hipMalloc(&c->occ, sizeof(uint64_t) * OCC_WORDS * cap) != hipSuccess) {
                 c->tiles_cap = 0;
@@ -440,7 +508,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             c->rootbits = nullptr;
             c->wprefix = nullptr;
             c->vitem_roots = nullptr;
-            const int64_t cap = std::max<int64_t>(vitems, c->vitems_cap * 3 / 2);
+            const int64_t cap = n_vitems;
             if (hipMalloc(&c->rootbits, sizeof(uint64_t) * VITEM_WORDS * cap) != hipSuccess ||
                 hipMalloc(&c->wprefix, sizeof(uint32_t) * VITEM_WORDS * cap) != hipSuccess ||
                 hipMalloc(&c->vitem_roots, sizeof(int32_t) * cap) != hipSuccess) {
@@ -452,21 +520,21 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         if (any_point_labels && labelled_points > c->pcell_cap) {
             if (c->pcell) (void)hipFree(c->pcell);
             c->pcell = nullptr;
-            const int64_t cap = std::max<int64_t>(labelled_points, c->pcell_cap * 3 / 2);
+            const int64_t cap = n_pcell;
             if (hipMalloc(&c->pcell, sizeof(int32_t) * std::max<int64_t>(cap, 1)) != hipSuccess) {
                 c->pcell_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate point records");
             }
             c->pcell_cap = cap;
         }
-        if ((any_point_labels || prune || any_score) && cells > c->aux_cells_cap) {
+        if (aux_needed && cells > c->aux_cells_cap) {
             if (c->cvid) (void)hipFree(c->cvid);
             if (c->segsize) (void)hipFree(c->segsize);
             if (c->vtruth) (void)hipFree(c->vtruth);
             c->cvid = nullptr;
             c->segsize = nullptr;
             c->vtruth = nullptr;
-            const int64_t cap = std::max<int64_t>(cells, c->aux_cells_cap * 3 / 2);
+            const int64_t cap = n_aux;
             if (hipMalloc(&c->cvid, sizeof(int32_t) * cap) != hipSuccess ||
                 hipMalloc(&c->segsize, sizeof(int32_t) * cap) != hipSuccess ||
                 hipMalloc(&c->vtruth, sizeof(int32_t) * cap) != hipSuccess) {
@@ -478,7 +546,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         if (border_slots > c->border_cap) {
             if (c->border) (void)hipFree(c->border);
             c->border = nullptr;
-            const int64_t cap = std::max<int64_t>(border_slots, c->border_cap * 3 / 2);
+            const int64_t cap = n_border;
             if (hipMalloc(&c->border, sizeof(int2) * cap) != hipSuccess) {
                 c->border_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate border slots");
@@ -492,7 +560,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 if (c->h_table[b]) (void)hipHostFree(c->h_table[b]);
                 c->h_table[b] = nullptr;
             }
-            const size_t cap = align_up(std::max(table_bytes, c->table_cap * 3 / 2), 4096);
+            const size_t cap = n_table;
             if (hipMalloc(&c->d_table, cap) != hipSuccess ||
                 hipHostMalloc(&c->h_table[0], cap, hipHostMallocDefault) != hipSuccess ||
                 hipHostMalloc(&c->h_table[1], cap, hipHostMallocDefault) != hipSuccess) {
@@ -534,7 +602,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
         d.scores = r.edge_counts;
         d.score_r = params->score_radius;
         d.pred = params->predicate;
-        d.min_seg = params->min_segment;
+        d.min_seg = mesh_only ? 0 : params->min_segment;
         d.cos_min = params->cos_min;
         d.H = p.H; d.W = p.W; d.s = p.s; d.Wp = p.Wp; d.wrap = p.wrap; d.TW = p.TW;
         d.n_tiles = p.n_tiles; d.tile_off = tile_off;
@@ -583,6 +651,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.max_frames = 1;
             cfg.post = prune || results[f].point_labels;
             cfg.score = results[f].edge_counts != nullptr;
+            cfg.mesh_only = mesh_only;
             cfg.grid = std::max(std::max(plan[f].n_tiles, plan[f].n_pblk), plan[f].n_vitem);
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table + offs[f]), ws, cfg, stream, ev);
@@ -625,6 +694,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             cfg.max_frames = n_frames;
             cfg.post = post;
             cfg.score = any_score;
+            cfg.mesh_only = mesh_only;
             cfg.grid = auto_grid;
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
@@ -634,7 +704,11 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
             // from the device table, so it serves every batch that fits the workspace.
             if (!c->graph_valid || c->graph_table_bytes != c->table_cap || c->graph_tile_cells != c->tile_cells ||
                 c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid || c->graph_post != post ||
-                c->graph_score != any_score) {
+                c->graph_score != any_score || c->graph_mesh_only != mesh_only) {
+                // a replay of the old graph may still run: wait for this
+                // context's earlier calls before destroying it
+                int rc = c->wait_idle();
+                if (rc) return rc;
                 c->drop_graph();
                 hipStream_t cap_stream;
                 e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
@@ -651,6 +725,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 cfg.max_frames = INT32_MAX;
                 cfg.post = post;
                 cfg.score = any_score;
+                cfg.mesh_only = mesh_only;
                 cfg.grid = auto_grid;
                 hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
                 e = hipStreamEndCapture(cap_stream, &c->graph);
@@ -668,6 +743,7 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
                 c->graph_grid = auto_grid;
                 c->graph_post = post;
                 c->graph_score = any_score;
+                c->graph_mesh_only = mesh_only;
             }
             e = hipGraphLaunch(c->graph_exec[c->graph_next], stream);
             c->graph_next ^= 1;
@@ -680,6 +756,25 @@ int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
     c->flip ^= 1;
     c->err.clear();
     return LIDAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
+                       const lidar_params_t* params, lidar_result_t* results, void* stream, int32_t launch) {
+    return mesh_call(c, frames, n_frames, params, results, stream, launch, CALL_SEGMENT);
+}
+
+int lidar_mesh_normals(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
+                       const lidar_params_t* params, lidar_result_t* results, void* stream, int32_t launch) {
+    return mesh_call(c, frames, n_frames, params, results, stream, launch, CALL_MESH_ONLY);
+}
+
+int lidar_label_grid(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
+                     const lidar_params_t* params, lidar_result_t* results, void* stream, int32_t launch) {
+    return mesh_call(c, frames, n_frames, params, results, stream, launch, CALL_LABEL_GRID);
 }
 
 }  // extern "C"

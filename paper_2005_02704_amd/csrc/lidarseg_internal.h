@@ -102,6 +102,7 @@ struct LaunchCfg {
     int max_frames;
     bool post = false;   // launch the segment-removal / point-label stage
     bool score = false;  // launch the edge-score stage
+    bool mesh_only = false;  // binning, mesh and normals only (no labelling stages)
 };
 
 constexpr int N_STAGES = 11;  // bin, count, geom, cc, merge, compress, flatten, scan, label, post, score

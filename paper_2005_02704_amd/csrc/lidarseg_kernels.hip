@@ -1236,6 +1236,23 @@ __global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ 
     }
 }
 
+// Mesh-only calls (no labelling stages): the key cells of every labelling
+// item go back to empty for the next call, as k_flatten does in a full chain,
+// and each frame's label count K is written as 0.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_reset(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    for (int b = blockIdx.x; b < hdr->total_vitems; b += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::vitem_off>(F, nf, b);
+        const int v0 = (b - fd->vitem_off) * VITEM;
+        if (v0 == 0 && threadIdx.x == 0) fd->counts[2] = 0;
+        const int c1 = min(v0 + VITEM, fd->H * fd->Wp);
+        uint64_t* keys = ws.keys + fd->cell_off;
+        for (int c = v0 + threadIdx.x; c < c1; c += NT) keys[c] = KEY_EMPTY;
+    }
+}
+
 // Rank bases, one frame per workgroup: each labelling item's root count is
 // replaced by the roots of the frame before the item (an exclusive scan in
 // firing order), and the frame's label count K is written.
@@ -1485,13 +1502,13 @@ __global__ __launch_bounds__(NT) void k_score(const BatchHeader* __restrict__ hd
 
 // The three tile kernels for one tile shape (TT threads, MAXC cells per tile).
 template <int TT, int MAXC>
-void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_tiles, int g_cc, hipStream_t stream,
-                        const std::function<void()>& mark) {
+void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_tiles, int g_cc, bool mesh_only,
+                        hipStream_t stream, const std::function<void()>& mark) {
     k_count<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
     mark();
     k_geom<TT, MAXC><<<g_tiles, TT, 0, stream>>>(d_hdr, ws);
     mark();
-    k_cc<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
+    if (!mesh_only) k_cc<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
     mark();
 }
 
@@ -1522,11 +1539,25 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
     mark();
     const int shape = cfg.tile_cells * 4 + cfg.tile_threads / 256;
     switch (shape) {
-        case 512 * 4 + 1: launch_tile_stages<256, 512>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
-        case 2048 * 4 + 1: launch_tile_stages<256, 2048>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
-        case 1024 * 4 + 2: launch_tile_stages<512, 1024>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
-        case 2048 * 4 + 2: launch_tile_stages<512, 2048>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
-        default: launch_tile_stages<256, 1024>(d_hdr, ws, g_tiles, g_cc, stream, mark); break;
+        case 512 * 4 + 1: launch_tile_stages<256, 512>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        case 2048 * 4 + 1: launch_tile_stages<256, 2048>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        case 1024 * 4 + 2: launch_tile_stages<512, 1024>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        case 2048 * 4 + 2: launch_tile_stages<512, 2048>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        default: launch_tile_stages<256, 1024>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+    }
+    if (cfg.mesh_only) {
+        // no labelling: the stage marks stay in place (zero time), and the key
+        // reset is timed as the flatten stage, where a full chain does it
+        mark();
+        mark();
+        k_reset<NT><<<g_vitem, NT, 0, stream>>>(d_hdr, ws);
+        mark();
+        mark();
+        mark();
+        mark();
+        mark();
+        const hipError_t le = hipGetLastError();
+        return le != hipSuccess ? le : e;
     }
     k_merge<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);
     mark();

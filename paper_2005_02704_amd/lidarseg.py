@@ -30,8 +30,9 @@ LIDAR_PRED_COSINE = 1
 
 # every symbol include/lidarseg.h declares
 EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lidar_last_error",
-           "lidar_query_sizes", "lidar_mesh_segment", "lidar_ctx_set_tuning", "lidar_ctx_set_profiling",
-           "lidar_ctx_stage_times")
+           "lidar_query_sizes", "lidar_mesh_segment", "lidar_mesh_normals", "lidar_label_grid",
+           "lidar_ctx_set_workspace_limit", "lidar_ctx_workspace_bytes", "lidar_ctx_set_tuning",
+           "lidar_ctx_set_profiling", "lidar_ctx_stage_times")
 LIDAR_N_STAGES = 11
 STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post", "score")
 LIDAR_MAX_SCORE_RADIUS = 8
@@ -96,6 +97,13 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(lidar_params_t), ctypes.POINTER(lidar_result_t),
                                      P, ctypes.c_int32]
     L.lidar_mesh_segment.restype = ctypes.c_int
+    for name in ("lidar_mesh_normals", "lidar_label_grid"):
+        getattr(L, name).argtypes = L.lidar_mesh_segment.argtypes
+        getattr(L, name).restype = ctypes.c_int
+    L.lidar_ctx_set_workspace_limit.argtypes = [P, ctypes.c_uint64]
+    L.lidar_ctx_set_workspace_limit.restype = ctypes.c_int
+    L.lidar_ctx_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
+    L.lidar_ctx_workspace_bytes.restype = ctypes.c_int
     L.lidar_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lidar_ctx_set_tuning.restype = ctypes.c_int
     L.lidar_ctx_set_profiling.argtypes = [P, ctypes.c_int32]
@@ -148,14 +156,15 @@ class Outputs:
     """Caller-owned device outputs of one frame (torch tensors at full capacity)."""
 
     def __init__(self, sensor: SensorGeometry, device, with_vertex_point=True, n_points: int = 0,
-                 scores: bool = False):
+                 scores: bool = False, with_labels: bool = True):
         """n_points > 0 also allocates point_labels (every input point's label);
-        scores allocates edge_counts (edge scores against the frame's truth ids)."""
+        scores allocates edge_counts (edge scores against the frame's truth ids);
+        with_labels=False leaves labels out (lidar_mesh_normals writes none)."""
         import torch
         V, T = lidar_query_sizes(sensor)
         self.vertices = torch.empty((max(V, 1), 3), dtype=torch.float32, device=device)
         self.normals = torch.empty((max(V, 1), 3), dtype=torch.float32, device=device)
-        self.labels = torch.empty(max(V, 1), dtype=torch.int32, device=device)
+        self.labels = torch.empty(max(V, 1), dtype=torch.int32, device=device) if with_labels else None
         self.triangles = torch.empty((max(T, 1), 3), dtype=torch.int32, device=device)
         self.vertex_point = torch.empty(max(V, 1), dtype=torch.int32, device=device) if with_vertex_point else None
         self.counts = torch.zeros(3, dtype=torch.int64, device=device)
@@ -163,7 +172,8 @@ class Outputs:
         self.edge_counts = torch.zeros(4, dtype=torch.int64, device=device) if scores else None
 
     def c_struct(self) -> lidar_result_t:
-        return lidar_result_t(self.vertices.data_ptr(), self.normals.data_ptr(), self.labels.data_ptr(),
+        return lidar_result_t(self.vertices.data_ptr(), self.normals.data_ptr(),
+                              self.labels.data_ptr() if self.labels is not None else None,
                               self.triangles.data_ptr(),
                               self.vertex_point.data_ptr() if self.vertex_point is not None else None,
                               self.counts.data_ptr(),
@@ -175,7 +185,8 @@ class Outputs:
         V, T, K = (int(x) for x in self.counts.cpu())
         if V < 0 or T < 0 or K < 0:
             raise LidarError(LIDAR_EDEVICE, "the frame's device work failed (counts = -1)")
-        return dict(vertices=self.vertices[:V], normals=self.normals[:V], labels=self.labels[:V],
+        return dict(vertices=self.vertices[:V], normals=self.normals[:V],
+                    labels=self.labels[:V] if self.labels is not None else None,
                     triangles=self.triangles[:T],
                     vertex_point=self.vertex_point[:V] if self.vertex_point is not None else None,
                     point_labels=self.point_labels, counts=(V, T, K),
@@ -243,16 +254,35 @@ class LidarContext:
             results[f] = outputs[f].c_struct()
         return (frames, n, params, results, keep)
 
-    def lidar_mesh_segment(self, prepared, stream=None, launch: str | int = "batched"):
-        """Enqueue lidar_mesh_segment on `stream` (torch stream; default: current)."""
+    def _call(self, fn, prepared, stream, launch):
         import torch
         frames, n, params, results, _keep = prepared
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         mode = LAUNCH[launch] if isinstance(launch, str) else int(launch)
-        rc = self._L.lidar_mesh_segment(self._h, frames, n, ctypes.byref(params), results,
-                                        ctypes.c_void_p(stream.cuda_stream), mode)
-        self._check(rc)
+        self._check(fn(self._h, frames, n, ctypes.byref(params), results, ctypes.c_void_p(stream.cuda_stream), mode))
+
+    def lidar_mesh_segment(self, prepared, stream=None, launch: str | int = "batched"):
+        """Enqueue lidar_mesh_segment on `stream` (torch stream; default: current)."""
+        self._call(self._L.lidar_mesh_segment, prepared, stream, launch)
+
+    def lidar_mesh_normals(self, prepared, stream=None, launch: str | int = "batched"):
+        """Enqueue lidar_mesh_normals (binning, mesh and normals; no labels)."""
+        self._call(self._L.lidar_mesh_normals, prepared, stream, launch)
+
+    def lidar_label_grid(self, prepared, stream=None, launch: str | int = "batched"):
+        """Enqueue lidar_label_grid (labels of caller-given normals)."""
+        self._call(self._L.lidar_label_grid, prepared, stream, launch)
+
+    def set_workspace_limit(self, max_bytes: int):
+        """Device workspace bytes this context may hold (0 = no limit)."""
+        self._check(self._L.lidar_ctx_set_workspace_limit(self._h, int(max_bytes)))
+
+    def workspace_bytes(self) -> int:
+        """Device workspace bytes the context holds now."""
+        v = ctypes.c_uint64()
+        self._check(self._L.lidar_ctx_workspace_bytes(self._h, ctypes.byref(v)))
+        return int(v.value)
 
 
 def make_params(r_min=1.0, r_max=60.0, thr=(0.2, 0.2, 0.2), predicate=LIDAR_PRED_COMPONENTS, cos_min=0.0,
