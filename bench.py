@@ -156,6 +156,18 @@ def accuracy_run(args, lp, synth, torch, ctx, frames, geos, stream):
             "batch": batch, "paper_shape_32x1800": paper, "paper_shape_environments": n_env}
 
 
+def cpu_model():
+    """The host CPU's model name, as the kernel reports it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,7 +381,7 @@ def main():
         rate_n = done_n / (time.perf_counter() - t)
         cpu = {"value": round(rate_n, 1), "unit": "points/s", "cores": threads, "kind": "oracle",
                "sample": f"{n_n} sweeps ({done_n} points) of the same batch on {threads} threads, one sweep per "
-                         f"task; host has {os.cpu_count()} CPUs",
+                         f"task; host has {os.cpu_count()} CPUs ({cpu_model()})",
                "single_thread_points_per_s": round(rate_1, 1),
                "single_thread_sample": f"first {n_1} of the {args.frames} sweeps ({done_1} points)"}
         log(f"  oracle: {rate_n:.0f} points/s on {threads} threads, {rate_1:.0f} points/s on one")
@@ -393,6 +405,7 @@ def main():
                    "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
                    "launch": best, "seed": args.seed, "launch_shape": shape, "launch_shape_source": shape_src},
         "forms": forms,
+        "vertices_per_s": round(V / (ms_best * 1e-3), 1),
         "path_algorithmic_gbs": round(path_gbs, 1),
         "roofline": roofline,
         "served": served,
