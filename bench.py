@@ -48,7 +48,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-STAGE_KERNEL = {"bin": "k_bin", "count": "k_count", "geom": "k_geom", "cc": "k_cc", "merge": "k_merge",
+STAGE_KERNEL = {"bin": "k_bin", "geom": "k_geom", "cc": "k_cc", "merge": "k_merge",
                 "compress": "k_compress", "flatten": "k_flatten", "scan": "k_scan", "label": "k_resolve",
                 "post": "k_post", "score": "k_score"}
 

@@ -179,3 +179,25 @@ def test_workspace_limit():
     finally:
         a.close()
         b.close()
+
+
+def test_stage_times(ctx):
+    """Per-stage timing: every stage of a batched call is timed once; a
+    mesh-only call times bin, geom and the key reset (flatten) only."""
+    import paper_2005_02704_amd as lp
+    items = _batch()
+    ctx.set_profiling(True)
+    try:
+        ctx.stage_times()
+        run_gpu(ctx, [it + (None,) for it in items], launch="batched")
+        full = ctx.stage_times()
+        _mesh_normals(ctx, items, "batched")
+        mesh = ctx.stage_times()
+    finally:
+        ctx.set_profiling(False)
+    assert tuple(full) == lp.STAGES == tuple(mesh)
+    assert all(n == 1 for _, n in full.values())
+    for k in ("bin", "geom", "cc", "merge", "compress", "flatten", "scan", "label"):
+        assert full[k][0] > 0, k
+    for k in ("bin", "geom", "flatten"):
+        assert mesh[k][0] > 0, k
