@@ -48,7 +48,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-STAGE_KERNEL = {"bin": "k_bin", "geom": "k_geom", "cc": "k_cc", "merge": "k_merge",
+STAGE_KERNEL = {"bin": "k_bin", "count": "k_count", "geom": "k_geom", "cc": "k_cc", "merge": "k_merge",
                 "compress": "k_compress", "flatten": "k_flatten", "scan": "k_scan", "label": "k_resolve",
                 "post": "k_post", "score": "k_score"}
 
@@ -236,6 +236,7 @@ def main():
         from paper_2005_02704_amd import autotune
         shape = autotune.apply(ctx, geos)
         shape_src = f"autotuned table, class {autotune.batch_class(geos)}"
+    if_shape, n_flight = shape, args.in_flight
     log(f"launch shape {shape} ({shape_src})")
     inputs = [(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)]
     outs = [lp.Outputs(g, dev) for g in geos]
@@ -272,25 +273,26 @@ def main():
     counts = np.array([[int(x) for x in o.counts.cpu()] for o in outs])
     V, T = int(counts[:, 0].sum()), int(counts[:, 1].sum())
     log(f"  graph: {ms_graph:.3f} ms/step (host enqueue {host_ms['graph']:.3f} ms/step)  V={V} T={T}")
-    forms = {"graph": {"points_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4)}}
+    forms = {"graph": {"points_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4),
+                       "launch_shape": shape}}
     for form in ("batched", "plain"):
         if form not in args.forms.split(","):
             continue
         log(f"timing {form} launches")
         ms = run(form, args.steps, args.warmup)
         log(f"  {form}: {ms:.3f} ms/step (host enqueue {host_ms[form]:.3f} ms/step)")
-        forms[form] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4)}
-    if args.in_flight > 1 and "batched" in args.forms.split(","):
+        forms[form] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4), "launch_shape": shape}
+    if n_flight > 1 and "batched" in args.forms.split(","):
         # the batched form with several batches in flight: each step is still one
         # whole call over the batch, on one of `in_flight` contexts (workspace and
         # outputs of its own) and streams, taken in turn, so one batch's
         # latency-bound labelling stages overlap the next batch's mesh stages
-        name = f"batched_x{args.in_flight}"
-        log(f"timing batched launches, {args.in_flight} batches in flight")
+        name = f"batched_x{n_flight}"
+        log(f"timing batched launches, {n_flight} batches in flight, launch shape {if_shape}")
         extra = []
-        for _ in range(args.in_flight):
+        for _ in range(n_flight):
             c2 = lp.LidarContext(0)
-            c2.set_tuning(shape["grid"], shape["tile_cells"], shape["tile_threads"])
+            c2.set_tuning(if_shape["grid"], if_shape["tile_cells"], if_shape["tile_threads"])
             o2 = [lp.Outputs(g, dev) for g in geos]
             extra.append((c2, c2.prepare(inputs, params, o2), torch.cuda.Stream(dev), o2))
         ms = run("batched", args.steps, args.warmup, [(c2, p2, s2) for c2, p2, s2, _ in extra], name)
@@ -299,7 +301,8 @@ def main():
         log(f"  {name}: {ms:.3f} ms/step (host enqueue {host_ms[name]:.3f} ms/step), outputs as one in flight: {same}")
         if not same:
             raise RuntimeError("batches in flight gave other outputs than one batch alone")
-        forms[name] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4)}
+        forms[name] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                       "launch_shape": if_shape}
         for c2, _, _, _ in extra:
             c2.close()
         del extra
@@ -403,7 +406,8 @@ def main():
         "config": {"workload": f"batched {args.frames} uneven street sweeps (rings 16/32/64/128, "
                                f"azimuth 1024/2048/4096, s=1)", "frames": args.frames,
                    "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
-                   "launch": best, "seed": args.seed, "launch_shape": shape, "launch_shape_source": shape_src},
+                   "launch": best, "seed": args.seed, "launch_shape": forms[best]["launch_shape"],
+                   "launch_shape_source": shape_src},
         "forms": forms,
         "vertices_per_s": round(V / (ms_best * 1e-3), 1),
         "path_algorithmic_gbs": round(path_gbs, 1),

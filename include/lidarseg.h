@@ -202,15 +202,15 @@ int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_c
 
 /* Per-stage timing of plain and batched launches (not of graph replays), with
  * HIP events recorded on the launch stream around each kernel of the chain.
- * Stages, in order: bin, geom (occupancy, vertex and triangle counts and
- * bases, numbering, mesh triangles, normals), cc (similar joins, local
+ * Stages, in order: bin, count (vertices, triangles and occupancy per tile),
+ * geom (numbering, mesh triangles, normals), cc (similar joins, local
  * segments), merge (segments across tiles), compress (pointer jumping on the
  * merged segments), flatten (segment roots), scan (rank bases of the roots),
  * label, post (segment removal and point labels; zero time when neither is
  * asked for), score (edge scores; zero time unless asked for).  In
  * lidar_mesh_normals calls the labelling stages take zero time and flatten is
  * the reset of the key grid.  Enabling costs one event per kernel. */
-#define LIDAR_N_STAGES 10
+#define LIDAR_N_STAGES 11
 int lidar_ctx_set_profiling(lidar_ctx* ctx, int32_t enable);
 /* Waits for the profiled calls, then writes the summed milliseconds and the
  * number of timed launches of each stage (arrays of LIDAR_N_STAGES; launches

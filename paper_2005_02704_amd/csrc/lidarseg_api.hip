@@ -32,8 +32,7 @@ struct lidar_ctx {
     uint64_t* keys = nullptr;
     int32_t* forest = nullptr;    // same capacity as keys
     int64_t keys_cap = 0;
-    char* tile_buf = nullptr;     // tile states (tiles_cap uint64), control words (CTL_WORDS uint64),
-                                  // vertices per tile (tiles_cap int32)
+    int32_t* tile_buf = nullptr;  // 2 int32 arrays of tiles_cap: vertices, triangles per tile
     uint64_t* occ = nullptr;      // OCC_WORDS per tile
     int64_t tiles_cap = 0;
     uint64_t* rootbits = nullptr; // VITEM_WORDS per labelling item
@@ -76,8 +75,7 @@ struct lidar_ctx {
     static uint64_t ws_bytes(int64_t keys_n, int64_t tiles_n, int64_t vitems_n, int64_t pcell_n, int64_t aux_n,
                              int64_t border_n, size_t table_n) {
         return (uint64_t)keys_n * (sizeof(uint64_t) + sizeof(int32_t)) +
-               (uint64_t)tiles_n * (sizeof(uint64_t) * STATE_STRIDE + sizeof(int32_t) + OCC_WORDS * sizeof(uint64_t)) +
-               (tiles_n > 0 ? sizeof(uint64_t) * CTL_WORDS : 0) +
+               (uint64_t)tiles_n * (2 * sizeof(int32_t) + OCC_WORDS * sizeof(uint64_t)) +
                (uint64_t)vitems_n * (VITEM_WORDS * (sizeof(uint64_t) + sizeof(uint32_t)) + sizeof(int32_t)) +
                (uint64_t)pcell_n * sizeof(int32_t) +
                (uint64_t)aux_n * 3 * sizeof(int32_t) + (uint64_t)border_n * sizeof(int2) + (uint64_t)table_n;
@@ -124,9 +122,8 @@ struct lidar_ctx {
         Workspace ws;
         ws.keys = keys;
         ws.forest = forest;
-        ws.tile_state = reinterpret_cast<uint64_t*>(tile_buf);
-        ws.ctl = reinterpret_cast<int32_t*>(tile_buf + sizeof(uint64_t) * STATE_STRIDE * tiles_cap);
-        ws.tile_v = reinterpret_cast<int32_t*>(tile_buf + sizeof(uint64_t) * (STATE_STRIDE * tiles_cap + CTL_WORDS));
+        ws.tile_v = tile_buf;
+        ws.tile_t = tile_buf + tiles_cap;
         ws.occ = occ;
         ws.rootbits = rootbits;
         ws.wprefix = wprefix;
@@ -497,8 +494,7 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
             c->tile_buf = nullptr;
             c->occ = nullptr;
             const int64_t cap = n_tiles;
-            if (hipMalloc(&c->tile_buf, sizeof(uint64_t) * (STATE_STRIDE * cap + CTL_WORDS) + sizeof(int32_t) * cap) !=
-                    hipSuccess ||
+            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess ||
                 hipMalloc(&c->occ, sizeof(uint64_t) * OCC_WORDS * cap) != hipSuccess) {
                 c->tiles_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate tile arrays");

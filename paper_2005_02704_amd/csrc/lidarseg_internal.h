@@ -67,13 +67,8 @@ static_assert(sizeof(FrameDesc) % 8 == 0, "desc alignment");
 struct Workspace {
     uint64_t* keys;       // (float(r^2) bits << 32) | point index; KEY_EMPTY = no point
     int32_t* forest;      // union-find parent of each vertex, as a batch-wide position
-    int32_t* tile_v;      // vertices owned by each tile (written by k_geom)
-    uint64_t* tile_state; // per tile, published by k_geom for the tiles after it: status
-                          // (bits 62-63: 0 none, 1 the tile's own counts, 2 counts of the
-                          // frame's tiles up to and including it), triangles (bits 31-61),
-                          // vertices (bits 0-30)
-    int32_t* ctl;         // [q * CLAIM_STRIDE] tile counter q of k_geom; [FAIL_SLOT] nonzero
-                          // after a look-back gave up waiting (the batch's counts are then -1)
+    int32_t* tile_v;      // vertices owned by each tile
+    int32_t* tile_t;      // triangles anchored in each tile
     uint64_t* occ;        // per tile, OCC_WORDS words: occupancy of its own cells (bit l of
                           // the tile's cell sequence, firing order from its first column)
     uint64_t* rootbits;   // per 64 vertex slots: which vertices are segment roots
@@ -110,14 +105,7 @@ struct LaunchCfg {
     bool mesh_only = false;  // binning, mesh and normals only (no labelling stages)
 };
 
-constexpr int SPIN_LIMIT = 1 << 15;  // polls of a tile state before a look-back gives up
-constexpr int N_CLAIM = 64;          // tile counters of k_geom (workgroup b claims from counter b % N_CLAIM)
-constexpr int CLAIM_STRIDE = 32;     // int32 slots between counters: one 128-byte line each, since
-                                     // atomics on one line are served one after another
-constexpr int FAIL_SLOT = N_CLAIM * CLAIM_STRIDE;               // ctl slot of the failure flag
-constexpr int CTL_WORDS = (FAIL_SLOT + CLAIM_STRIDE) / 2;       // uint64 words of ctl
-constexpr int STATE_STRIDE = 16;     // uint64 words per tile state: one 128-byte line each
-constexpr int N_STAGES = 10;  // bin, geom, cc, merge, compress, flatten, scan, label, post, score
+constexpr int N_STAGES = 11;  // bin, count, geom, cc, merge, compress, flatten, scan, label, post, score
 
 // Tile shapes (cells per tile, threads per tile workgroup) the kernels are built for.
 bool tile_shape_supported(int tile_cells, int tile_threads);

@@ -1,20 +1,18 @@
 // HIP kernels for gfx950 (MI355X): bin -> sub-sample -> mesh -> normals -> labels.
 //
-// One batch of frames runs as a chain of eight grid-stride kernels (ten when
+// One batch of frames runs as a chain of nine grid-stride kernels (eleven when
 // point labels, segment removal or edge scores are asked for); each kernel
 // walks its work items (point blocks, lattice tiles, border slots, blocks of
 // vertex slots or frames) across every frame of the batch, reading the
 // per-frame descriptors from device memory, so the same launches (and the same
-// captured graph) serve any batch that fits the workspace.  One kernel waits
-// for other workgroups: k_geom, whose tiles take their vertex and triangle
-// bases from the tiles before them (a decoupled look-back over tiles handed
-// out in increasing order by a counter, with a bounded wait); no other kernel
-// waits for another workgroup.
+// captured graph) serve any batch that fits the workspace.  No kernel waits for
+// another workgroup, and no work item is handed out through a shared counter.
 //
 // Stage map (Mukherjee et al., PReMI 2019, Section 2):
 //   k_bin      points -> (ring, firing) cell, sub-sampling, nearest return     [opening paragraph]
-//   k_geom     per tile in LDS: occupancy, vertex and triangle numbering (bases
-//              by look-back), mesh triangles, normals                          [Mesh Construction,
+//   k_count    vertices, triangles and occupancy bits of each tile             [Mesh Construction]
+//   k_geom     per tile in LDS: vertex and triangle numbering, mesh triangles,
+//              normals                                                         [Mesh Construction,
 //                                                                               Normal Estimation]
 //   k_cc       per tile in LDS: similarity of joins, local segments           [Algorithm 1]
 //   k_merge    unions of the similar joins that cross tile borders             [Algorithm 1]
@@ -196,11 +194,6 @@ __global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ h
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
     const int nb = hdr->total_pblk;
-    // the tile states and the claim counter of k_geom start over with every chain
-    for (int t = blockIdx.x * NT + (int)threadIdx.x; t < hdr->total_tiles; t += (int)gridDim.x * NT)
-        ws.tile_state[(int64_t)t * STATE_STRIDE] = 0;
-    if (blockIdx.x == 0)
-        for (int q = (int)threadIdx.x; q <= N_CLAIM; q += NT) ws.ctl[q * CLAIM_STRIDE] = 0;  // counters, flag
     const int per = (nb + (int)gridDim.x - 1) / (int)gridDim.x;
     const int b0 = blockIdx.x * per, b1 = min(nb, b0 + per);
     int cur = -1;
@@ -307,6 +300,91 @@ __global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ h
                 const int ring = rings ? (int)rings[p] : ring_fp64(s_elev, H, z, rho2);
                 bin_store(keys, pcell, p, ring, firing_fp64(x, y, az0, dphi), W, H, s, r2);
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vertices and triangles owned by each tile (from the key grid alone), so that
+// the tile stages can number their vertices and triangles without waiting on
+// other tiles, and the occupancy bits of the tile's cells.
+// A vertex is an occupied cell; own anchor (i, k) with i+1 < H has triangle
+// T_a = (p, A, B) and T_b = (p, B, C) when all three corners are occupied.
+template <int NT, int MAXC>
+__global__ __launch_bounds__(NT) void k_count(const BatchHeader* __restrict__ hdr, Workspace ws) {
+    constexpr int NO = MAXC + MAX_RINGS;      // own cells + right column
+    constexpr int RO = (NO + NT - 1) / NT;
+    constexpr int NW = NT / 64;
+    __shared__ uint8_t socc[NO];
+    __shared__ int s_red[2][NW];
+    const FrameDesc* F = frames_of(hdr);
+    const int nf = hdr->n_frames;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
+        const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
+        const int H = fd->H, Wp = fd->Wp;
+        const float inv_h = 1.0f / (float)H;
+        const int k0 = (t - fd->tile_off) * fd->TW;
+        const int TWe = min(fd->TW, Wp - k0);
+        const int nown = H * TWe;
+        const bool inside = k0 + TWe < Wp;
+        const bool right = inside || fd->wrap;
+        const int64_t rbase = (int64_t)(inside ? k0 + TWe : 0) * H;
+        const uint64_t* keys = ws.keys + fd->cell_off;
+        const int64_t np = fd->n_points;
+        if (fd->scores && t == fd->tile_off && threadIdx.x < 4) fd->scores[threadIdx.x] = 0;
+        __syncthreads();  // the previous tile's readers are done
+        uint32_t key[RO];
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            key[r] = ~0u;
+            if (l < nown) key[r] = key_index(keys, (int64_t)k0 * H + l);
+            else if (l < nown + H && right) key[r] = key_index(keys, rbase + (l - nown));
+        }
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l < nown + H) socc[l] = occupied_index(key[r], np) ? 1 : 0;
+        }
+        __syncthreads();
+        int nv = 0, nt = 0;
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            if (l < nown && socc[l]) {
+                ++nv;
+                const int i = l - div_small(l, inv_h) * H;
+                if (i + 1 < H) {
+                    const int a = socc[l + 1], b = socc[l + H + 1], c = socc[l + H];
+                    nt += (a & b) + (b & c);
+                }
+            }
+        }
+        // occupancy words of the own cells (64-cell chunk r * NW + wv is one ballot)
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const int l = threadIdx.x + r * NT;
+            const int chunk = r * NW + wv;
+            const uint64_t m = __ballot(l < nown && socc[l]);
+            if (lane == 0 && chunk < MAXC / 64) ws.occ[(int64_t)t * OCC_WORDS + chunk] = m;
+        }
+        nv = wave_sum(nv);
+        nt = wave_sum(nt);
+        if (lane == 0) {
+            s_red[0][wv] = nv;
+            s_red[1][wv] = nt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int sv = 0, st = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                sv += s_red[0][w];
+                st += s_red[1][w];
+            }
+            ws.tile_v[t] = sv;
+            ws.tile_t[t] = st;
         }
     }
 }
@@ -444,7 +522,7 @@ template <int NT, int RN>
 __device__ __forceinline__ void number_cells(int (&vid)[RN], const int* s_cnt, int vbase, int vbase_next,
                                              int own_v, int nown, int lane, int wv) {
     constexpr int NW = NT / 64;
-    const int c = lane < RN * NW ? (s_cnt[lane] & 0xff) : 0;
+    const int c = lane < RN * NW ? (s_cnt[lane] & 0xffff) : 0;
     int inc = c;
 #pragma unroll
     for (int d = 1; d < RN * NW; d <<= 1) {
@@ -459,84 +537,6 @@ __device__ __forceinline__ void number_cells(int (&vid)[RN], const int* s_cnt, i
         if (vid[r] < 0) continue;
         const int rank = pre + vid[r];
         vid[r] = (l < nown) ? vbase + rank : vbase_next + (rank - own_v);
-    }
-}
-
-// Tile states: status in bits 62-63, triangles in bits 31-61, vertices in bits
-// 0-30 (a frame has fewer than 2^29 cells, so every count and prefix fits).
-__device__ __forceinline__ uint64_t state_word(int status, int v, int tr) {
-    return ((uint64_t)status << 62) | ((uint64_t)(uint32_t)tr << 31) | (uint64_t)(uint32_t)v;
-}
-
-// Tile t's own vertices and triangles (from the per-chunk counts in s_agg:
-// vertices | triangles << 8), published in its state for the tiles after it
-// -- as a complete prefix when t is the frame's first tile -- and kept in
-// s_misc[2], s_misc[3] and tile_v[t].  Run by one wave.
-__device__ void publish_counts(const Workspace& ws, const FrameDesc* fd, int t, const int* s_agg, int nchunk,
-                               int lane, int* s_misc) {
-    const int c = lane < nchunk ? s_agg[lane] : 0;
-    const int own_v = wave_sum(c & 0xff);
-    const int own_t = wave_sum(c >> 8);
-    if (lane == 0) {
-        __hip_atomic_store(ws.tile_state + (int64_t)t * STATE_STRIDE,
-                           state_word(t == fd->tile_off ? 2 : 1, own_v, own_t), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        s_misc[2] = own_v;
-        s_misc[3] = own_t;
-        ws.tile_v[t] = own_v;
-    }
-}
-
-// Vertex and triangle bases of tile t (the counts of the frame's tiles before
-// it) by a decoupled look-back, run by one wave after publish_counts: it walks
-// back over the states of the tiles before t, 64 at a time, summing counts up
-// to the nearest tile that has published a complete prefix (the frame's first
-// tile always has), and publishes t's own complete prefix.  A wait that
-// outlasts SPIN_LIMIT polls, or follows another tile's failed wait, sets the
-// failure flag and takes zero bases, which keep every write in bounds.  Writes
-// s_misc[0], s_misc[1] = vertex base, triangle base.
-__device__ void tile_bases(const Workspace& ws, const FrameDesc* fd, int t, int lane, int* s_misc) {
-    const int own_v = s_misc[2], own_t = s_misc[3];
-    const int f0 = fd->tile_off;
-    uint64_t* const st = ws.tile_state;
-    int pv = 0, pt = 0;
-    if (t > f0) {
-        int j = t - 1;
-        for (int polls = 0;;) {
-            const int idx = j - lane;
-            const uint64_t w = idx >= f0 ? __hip_atomic_load(st + (int64_t)idx * STATE_STRIDE, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT)
-                                         : state_word(2, 0, 0);
-            const int status = (int)(w >> 62);
-            const uint64_t done = __ballot(status == 2);
-            const uint64_t none = __ballot(status == 0);
-            // lanes up to (and including) the nearest complete prefix
-            const uint64_t upto = done ? ((done & (~done + 1ull)) << 1) - 1ull : ~0ull;
-            if (none & upto) {
-                const int failed = __builtin_amdgcn_readfirstlane(
-                    __hip_atomic_load(ws.ctl + FAIL_SLOT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                if (++polls > SPIN_LIMIT || failed) {
-                    if (lane == 0) atomicOr(ws.ctl + FAIL_SLOT, 1);
-                    pv = 0;
-                    pt = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-                continue;
-            }
-            const bool take = (upto >> lane) & 1ull;
-            pv += wave_sum(take ? (int)(w & 0x7fffffffull) : 0);
-            pt += wave_sum(take ? (int)((w >> 31) & 0x7fffffffull) : 0);
-            if (done) break;
-            j -= 64;
-        }
-        if (lane == 0)
-            __hip_atomic_store(st + (int64_t)t * STATE_STRIDE, state_word(2, pv + own_v, pt + own_t),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (lane == 0) {
-        s_misc[0] = pv;
-        s_misc[1] = pt;
     }
 }
 
@@ -560,27 +560,13 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
     static_assert(RN * NW <= 64, "one lane per (round, wave) in the prefix scan");
     __shared__ float4 sc[XC];         // (x, y, z, vertex id) by lx
     __shared__ int saux[MAXC];        // kept point index, then triangle start
-    __shared__ uint8_t socc[XC];      // occupancy of the staged cells by lx
     __shared__ int s_cnt[RN * NW];    // per round and wave: vertices | triangles << 16
-    __shared__ int s_agg[RN * NW];    // per round and wave: own vertices | own triangles << 8
     __shared__ int s_misc[4];         // vertex base, triangle base, own vertices, own triangles
-    __shared__ int s_tile;
 
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    // Tiles are claimed in increasing order from a counter, so every tile a
-    // look-back waits for belongs to a workgroup that is already running.
-    for (;;) {
-        __syncthreads();  // LDS of the previous tile is free
-        if (threadIdx.x == 0) {
-            const int nq = min(N_CLAIM, (int)gridDim.x);   // every counter has a workgroup
-            const int q = (int)blockIdx.x % nq;
-            s_tile = q + nq * atomicAdd(ws.ctl + q * CLAIM_STRIDE, 1);
-        }
-        __syncthreads();
-        const int t = s_tile;
-        if (t >= hdr->total_tiles) break;
+    for (int t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) {
         const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
         const int H = fd->H, Wp = fd->Wp, wrap = fd->wrap;
         const float inv_h = 1.0f / (float)H;
@@ -596,7 +582,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
         const int64_t np = fd->n_points;
         const int step_i = NT % H, step_c = NT / H;   // (column, ring) advance per round
         const int i0 = (int)threadIdx.x - div_small(threadIdx.x, inv_h) * H;
-        if (fd->scores && lt == 0 && threadIdx.x < 4) fd->scores[threadIdx.x] = 0;
+        __syncthreads();  // LDS of the previous tile is free
 
         // The loads of phases 1-3 go out at raised wave priority, so that a
         // workgroup starting a tile gets its memory requests in flight ahead of
@@ -625,43 +611,23 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
                 if (i >= H) { i -= H; ++col; }
             }
         }
-        // 2. occupancy of the staged cells; the tile's own vertices and
-        //    triangles, published before the coordinates are gathered so that
-        //    the tiles after it find them early
-#pragma unroll
-        for (int r = 0; r < RX; ++r) {
-            const int lx = threadIdx.x + r * NT;
-            if (lx < nx) socc[lx] = occupied(key[r], np) ? 1 : 0;
-        }
-        __syncthreads();
-        {
-            int i = i0;
-#pragma unroll
-            for (int r = 0; r < RN; ++r) {
-                const int l = threadIdx.x + NT * r;
-                const int lx = l + H;
-                const bool v = l < nown && socc[lx] != 0;
-                int ntri = 0;
-                if (v && i + 1 < H) {
-                    const int b = socc[lx + H + 1];
-                    ntri = (socc[lx + 1] & b) + (b & socc[lx + H]);
-                }
-                const uint64_t bo = __ballot(v);
-                const uint64_t b1 = __ballot(ntri & 1);
-                const uint64_t b2 = __ballot(ntri >> 1);
-                if (lane == 0) {
-                    const int chunk = r * NW + wv;
-                    s_agg[chunk] = __popcll(bo) | ((__popcll(b1) + 2 * __popcll(b2)) << 8);
-                    // occupancy words of the own cells, for the segment stage
-                    if (chunk < MAXC / 64) ws.occ[(int64_t)t * OCC_WORDS + chunk] = bo;
-                }
-                i += step_i;
-                if (i >= H) i -= H;
+        // 2. vertex and triangle bases: the counts of the frame's earlier tiles
+        if (wv == 0) {
+            int sv = 0, st = 0;
+#pragma unroll 4
+            for (int j = fd->tile_off + lane; j < t; j += 64) {
+                sv += ws.tile_v[j];
+                st += ws.tile_t[j];
+            }
+            sv = wave_sum(sv);
+            st = wave_sum(st);
+            if (lane == 0) {
+                s_misc[0] = sv;
+                s_misc[1] = st;
+                s_misc[2] = ws.tile_v[t];
+                s_misc[3] = ws.tile_t[t];
             }
         }
-        __syncthreads();
-        if (wv == 0) publish_counts(ws, fd, t, s_agg, RN * NW, lane, s_misc);
-
         // 3. the kept points
         {
             float cx[RX], cy[RX], cz[RX];
@@ -698,10 +664,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
                 int ntri = 0;
                 if (l < nscan) {
                     const int lx = l + H;
-                    v = socc[lx] != 0;
+                    v = sc[lx].x == sc[lx].x;
                     if (v && l < nown && i + 1 < H) {
-                        const int b = socc[lx + H + 1];
-                        ntri = (socc[lx + 1] & b) + (b & socc[lx + H]);
+                        const bool a = sc[lx + 1].x == sc[lx + 1].x;
+                        const bool b = sc[lx + H + 1].x == sc[lx + H + 1].x;
+                        const bool c = sc[lx + H].x == sc[lx + H].x;
+                        ntri = (int)(a && b) + (int)(b && c);
                     }
                 }
                 const uint64_t bv = __ballot(v);
@@ -714,8 +682,6 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
                 if (i >= H) i -= H;
             }
         }
-        __syncthreads();
-        if (wv == 0) tile_bases(ws, fd, t, lane, s_misc);
         __syncthreads();
         const int vbase = s_misc[0], tbase = s_misc[1], own_v = s_misc[2];
         const bool last_tile = lt + 1 == fd->n_tiles;
@@ -865,11 +831,15 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
         if (threadIdx.x == 0) s_nj = 0;
 
         // 1. occupancy of own cells and the right column, vertex bases
-        if (threadIdx.x == 0) {
-            // the complete prefix k_geom published, less the tile's own vertices
-            const int own = ws.tile_v[t];
-            s_misc[0] = (int)(ws.tile_state[(int64_t)t * STATE_STRIDE] & 0x7fffffffull) - own;
-            s_misc[1] = own;
+        if (wv == 0) {
+            int sv = 0;
+#pragma unroll 4
+            for (int j = fd->tile_off + lane; j < t; j += 64) sv += ws.tile_v[j];
+            sv = wave_sum(sv);
+            if (lane == 0) {
+                s_misc[0] = sv;
+                s_misc[1] = ws.tile_v[t];
+            }
         }
         int vid[RN];
 #pragma unroll
@@ -1276,10 +1246,7 @@ __global__ __launch_bounds__(NT) void k_reset(const BatchHeader* __restrict__ hd
     for (int b = blockIdx.x; b < hdr->total_vitems; b += gridDim.x) {
         const FrameDesc* fd = F + frame_of<&FrameDesc::vitem_off>(F, nf, b);
         const int v0 = (b - fd->vitem_off) * VITEM;
-        if (v0 == 0 && threadIdx.x == 0) {
-            fd->counts[2] = 0;
-            if (ws.ctl[FAIL_SLOT]) fd->counts[0] = fd->counts[1] = fd->counts[2] = -1;  // a look-back gave up
-        }
+        if (v0 == 0 && threadIdx.x == 0) fd->counts[2] = 0;
         const int c1 = min(v0 + VITEM, fd->H * fd->Wp);
         uint64_t* keys = ws.keys + fd->cell_off;
         for (int c = v0 + threadIdx.x; c < c1; c += NT) keys[c] = KEY_EMPTY;
@@ -1321,10 +1288,7 @@ __global__ __launch_bounds__(NT) void k_scan(const BatchHeader* __restrict__ hdr
             if (j < n) cnt[j] = run + before + inc - mine;
             run += total;
         }
-        if (threadIdx.x == 0) {
-            fd->counts[2] = run;
-            if (ws.ctl[FAIL_SLOT]) fd->counts[0] = fd->counts[1] = fd->counts[2] = -1;  // a look-back gave up
-        }
+        if (threadIdx.x == 0) fd->counts[2] = run;
     }
 }
 
@@ -1540,6 +1504,8 @@ __global__ __launch_bounds__(NT) void k_score(const BatchHeader* __restrict__ hd
 template <int TT, int MAXC>
 void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_tiles, int g_cc, bool mesh_only,
                         hipStream_t stream, const std::function<void()>& mark) {
+    k_count<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
+    mark();
     k_geom<TT, MAXC><<<g_tiles, TT, 0, stream>>>(d_hdr, ws);
     mark();
     if (!mesh_only) k_cc<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);

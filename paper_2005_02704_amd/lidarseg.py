@@ -33,8 +33,8 @@ EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lid
            "lidar_query_sizes", "lidar_mesh_segment", "lidar_mesh_normals", "lidar_label_grid",
            "lidar_ctx_set_workspace_limit", "lidar_ctx_workspace_bytes", "lidar_ctx_set_tuning",
            "lidar_ctx_set_profiling", "lidar_ctx_stage_times")
-LIDAR_N_STAGES = 10
-STAGES = ("bin", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post", "score")
+LIDAR_N_STAGES = 11
+STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post", "score")
 LIDAR_MAX_SCORE_RADIUS = 8
 
 
