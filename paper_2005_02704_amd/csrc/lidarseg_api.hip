@@ -32,7 +32,7 @@ struct lidar_ctx {
     uint64_t* keys = nullptr;
     int32_t* forest = nullptr;    // same capacity as keys
     int64_t keys_cap = 0;
-    int32_t* tile_buf = nullptr;  // 2 int32 arrays of tiles_cap: vertices, triangles per tile
+    int32_t* tile_buf = nullptr;  // 3 int32 arrays of tiles_cap: vertices, triangles, vertex base per tile
     uint64_t* occ = nullptr;      // OCC_WORDS per tile
     int64_t tiles_cap = 0;
     uint64_t* rootbits = nullptr; // VITEM_WORDS per labelling item
@@ -75,7 +75,7 @@ struct lidar_ctx {
     static uint64_t ws_bytes(int64_t keys_n, int64_t tiles_n, int64_t vitems_n, int64_t pcell_n, int64_t aux_n,
                              int64_t border_n, size_t table_n) {
         return (uint64_t)keys_n * (sizeof(uint64_t) + sizeof(int32_t)) +
-               (uint64_t)tiles_n * (2 * sizeof(int32_t) + OCC_WORDS * sizeof(uint64_t)) +
+               (uint64_t)tiles_n * (3 * sizeof(int32_t) + OCC_WORDS * sizeof(uint64_t)) +
                (uint64_t)vitems_n * (VITEM_WORDS * (sizeof(uint64_t) + sizeof(uint32_t)) + sizeof(int32_t)) +
                (uint64_t)pcell_n * sizeof(int32_t) +
                (uint64_t)aux_n * 3 * sizeof(int32_t) + (uint64_t)border_n * sizeof(int2) + (uint64_t)table_n;
@@ -124,6 +124,7 @@ struct lidar_ctx {
         ws.forest = forest;
         ws.tile_v = tile_buf;
         ws.tile_t = tile_buf + tiles_cap;
+        ws.tile_vbase = tile_buf + 2 * tiles_cap;
         ws.occ = occ;
         ws.rootbits = rootbits;
         ws.wprefix = wprefix;
@@ -494,7 +495,7 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
             c->tile_buf = nullptr;
             c->occ = nullptr;
             const int64_t cap = n_tiles;
-            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 2 * cap) != hipSuccess ||
+            if (hipMalloc(&c->tile_buf, sizeof(int32_t) * 3 * cap) != hipSuccess ||
                 hipMalloc(&c->occ, sizeof(uint64_t) * OCC_WORDS * cap) != hipSuccess) {
                 c->tiles_cap = 0;
                 return c->fail(LIDAR_ENOMEM, "cannot allocate tile arrays");

@@ -69,6 +69,7 @@ struct Workspace {
     int32_t* forest;      // union-find parent of each vertex, as a batch-wide position
     int32_t* tile_v;      // vertices owned by each tile
     int32_t* tile_t;      // triangles anchored in each tile
+    int32_t* tile_vbase;  // vertices of the frame's tiles before each tile (written by k_geom)
     uint64_t* occ;        // per tile, OCC_WORDS words: occupancy of its own cells (bit l of
                           // the tile's cell sequence, firing order from its first column)
     uint64_t* rootbits;   // per 64 vertex slots: which vertices are segment roots

@@ -685,9 +685,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
         __syncthreads();
         const int vbase = s_misc[0], tbase = s_misc[1], own_v = s_misc[2];
         const bool last_tile = lt + 1 == fd->n_tiles;
-        if (threadIdx.x == 0 && last_tile) {
-            fd->counts[0] = vbase + own_v;
-            fd->counts[1] = tbase + s_misc[3];
+        if (threadIdx.x == 0) {
+            ws.tile_vbase[t] = vbase;  // for the segment stage
+            if (last_tile) {
+                fd->counts[0] = vbase + own_v;
+                fd->counts[1] = tbase + s_misc[3];
+            }
         }
         {
             // triangle starts: the same scan over the upper halves
@@ -831,15 +834,9 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
         if (threadIdx.x == 0) s_nj = 0;
 
         // 1. occupancy of own cells and the right column, vertex bases
-        if (wv == 0) {
-            int sv = 0;
-#pragma unroll 4
-            for (int j = fd->tile_off + lane; j < t; j += 64) sv += ws.tile_v[j];
-            sv = wave_sum(sv);
-            if (lane == 0) {
-                s_misc[0] = sv;
-                s_misc[1] = ws.tile_v[t];
-            }
+        if (threadIdx.x == 0) {
+            s_misc[0] = ws.tile_vbase[t];  // k_geom summed the counts of the tiles before
+            s_misc[1] = ws.tile_v[t];
         }
         int vid[RN];
 #pragma unroll

@@ -252,6 +252,9 @@ class LidarContext:
                                       truth.data_ptr() if truth is not None and truth.numel() else None,
                                       rings.data_ptr() if rings is not None and rings.numel() else None)
             results[f] = outputs[f].c_struct()
+            # the prepared call holds the tensors whose pointers it carries, so
+            # none of them is freed (and its memory reused) while the call lives
+            keep.append((xyz, normals_in, truth, rings, outputs[f]))
         return (frames, n, params, results, keep)
 
     def _call(self, fn, prepared, stream, launch):
