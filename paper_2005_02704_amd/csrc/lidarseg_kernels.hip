@@ -998,7 +998,21 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
         }
         __syncthreads();
 
-        // 7. local roots: the smallest cell of each local tree (no writes while reading)
+        // 7. local roots: the smallest cell of each local tree.  Two passes of
+        //    pointer jumping first (each roughly halves every path; a parent is
+        //    only ever replaced by an ancestor, so concurrent readers still reach
+        //    the root), then each cell's walk.
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int r = 0; r < RN; ++r) {
+                const int l = threadIdx.x + NT * r;
+                if (l >= nown) continue;
+                const int p = sparent[l];
+                const int gp = sparent[p];
+                if (gp != p) sparent[l] = gp;
+            }
+            __syncthreads();
+        }
         int* const forest = ws.forest;
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
