@@ -292,7 +292,8 @@ def main():
         extra = []
         for _ in range(n_flight):
             c2 = lp.LidarContext(0)
-            c2.set_tuning(if_shape["grid"], if_shape["tile_cells"], if_shape["tile_threads"])
+            from paper_2005_02704_amd import autotune
+            autotune.set_shape(c2, if_shape)
             o2 = [lp.Outputs(g, dev) for g in geos]
             extra.append((c2, c2.prepare(inputs, params, o2), torch.cuda.Stream(dev), o2))
         ms = run("batched", args.steps, args.warmup, [(c2, p2, s2) for c2, p2, s2, _ in extra], name)

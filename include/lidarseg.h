@@ -200,6 +200,12 @@ int lidar_ctx_workspace_bytes(const lidar_ctx* ctx, uint64_t* held_bytes);
  * 1024 cells or 256 threads.  Results do not depend on the shape. */
 int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_cells, int32_t tile_threads);
 
+/* Workgroups of one stage (index in the order of the stage list below) in
+ * batched and graph launches of later calls, in place of its share of the
+ * grid set by lidar_ctx_set_tuning; 0 restores that share.  Results do not
+ * depend on it. */
+int lidar_ctx_set_stage_grid(lidar_ctx* ctx, int32_t stage, int32_t workgroups);
+
 /* Per-stage timing of plain and batched launches (not of graph replays), with
  * HIP events recorded on the launch stream around each kernel of the chain.
  * Stages, in order: bin, count (vertices, triangles and occupancy per tile),

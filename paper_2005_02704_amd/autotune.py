@@ -9,6 +9,9 @@ favour big tiles, many narrow ones more workgroups.  This module
   * classifies a batch (ring count, sampled width, number of frames),
   * times every candidate shape on a prepared batch with HIP events on the
     launch stream (the whole chain, median of a few replays),
+  * then, in the winning shape, times each stage's kernel (HIP events) at other
+    workgroup counts and keeps a stage's own count where it is faster, when the
+    whole call is faster with them,
   * keeps the winners in a JSON table (`tune_table.json` next to this file),
   * and looks a batch's shape up in that table.
 
@@ -27,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(HERE, "tune_table.json")
 
 TILE_SHAPES = ((1024, 256), (512, 256), (2048, 256), (1024, 512), (2048, 512))
-GRIDS = (1024, 2048, 4096)
+GRIDS = (1024, 1536, 2048, 3072, 4096, 6144)
 DEFAULT = {"grid": 0, "tile_cells": 1024, "tile_threads": 256}
 
 
@@ -55,25 +58,37 @@ def load_table(path: str = TABLE_PATH) -> dict:
 
 
 def lookup(geometries, table: dict | None = None) -> dict:
-    """Tuned shape for this batch, or the library default when its class is absent."""
+    """Tuned shape for this batch, or the library default when its class is absent:
+    grid, tile_cells, tile_threads and stage_grids ({stage: workgroups})."""
     table = load_table() if table is None else table
     entry = table.get(batch_class(geometries))
     if not entry:
-        return dict(DEFAULT)
-    return {k: int(entry[k]) for k in ("grid", "tile_cells", "tile_threads")}
+        return {**DEFAULT, "stage_grids": {}}
+    shape = {k: int(entry[k]) for k in ("grid", "tile_cells", "tile_threads")}
+    shape["stage_grids"] = {k: int(v) for k, v in entry.get("stage_grids", {}).items()}
+    return shape
+
+
+def set_shape(ctx, shape: dict) -> None:
+    """Apply a shape (as lookup returns it) to a LidarContext."""
+    from .lidarseg import STAGES
+    ctx.set_tuning(shape["grid"], shape["tile_cells"], shape["tile_threads"])
+    grids = shape.get("stage_grids", {})
+    for stage in STAGES:
+        ctx.set_stage_grid(stage, grids.get(stage, 0))
 
 
 def apply(ctx, geometries, table: dict | None = None) -> dict:
     """Set the tuned shape of this batch on a LidarContext; returns it."""
     shape = lookup(geometries, table)
-    ctx.set_tuning(shape["grid"], shape["tile_cells"], shape["tile_threads"])
+    set_shape(ctx, shape)
     return shape
 
 
 def time_shape(ctx, prepared, stream, shape, launch="graph", reps=12, warm=3) -> float:
     """Median milliseconds of one call with this shape (events on the launch stream)."""
     import torch
-    ctx.set_tuning(shape["grid"], shape["tile_cells"], shape["tile_threads"])
+    set_shape(ctx, shape)
     for _ in range(warm):
         ctx.lidar_mesh_segment(prepared, stream, launch)
     torch.cuda.synchronize()
@@ -89,6 +104,47 @@ def time_shape(ctx, prepared, stream, shape, launch="graph", reps=12, warm=3) ->
     return statistics.median(times)
 
 
+STAGE_GRIDS = (256, 512, 1024, 1536, 2048, 3072, 4096, 6144, 8192)
+TUNED_STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "label")
+
+
+def stage_ms(ctx, prepared, stream, reps=10) -> dict:
+    """Milliseconds per launch of every stage over `reps` batched calls (events)."""
+    import torch
+    for _ in range(2):
+        ctx.lidar_mesh_segment(prepared, stream, "batched")
+    torch.cuda.synchronize()
+    ctx.stage_times()
+    ctx.set_profiling(True)
+    for _ in range(reps):
+        ctx.lidar_mesh_segment(prepared, stream, "batched")
+    torch.cuda.synchronize()
+    st = ctx.stage_times()
+    ctx.set_profiling(False)
+    return {k: ms / n for k, (ms, n) in st.items() if n}
+
+
+def tune_stage_grids(ctx, prepared, stream, shape, log=None) -> dict:
+    """In `shape`, each tuned stage's workgroup count that beats its share of the
+    grid by at least 2 % in that stage's own time; returns {stage: workgroups}."""
+    set_shape(ctx, {**shape, "stage_grids": {}})
+    base = stage_ms(ctx, prepared, stream)
+    chosen = {}
+    for stage in TUNED_STAGES:
+        best_g, best = 0, base[stage]
+        for g in STAGE_GRIDS:
+            ctx.set_stage_grid(stage, g)
+            ms = stage_ms(ctx, prepared, stream)[stage]
+            if ms < best * 0.98:
+                best_g, best = g, ms
+        ctx.set_stage_grid(stage, best_g)
+        if best_g:
+            chosen[stage] = best_g
+            if log:
+                log(f"  stage {stage}: {best_g} workgroups, {best:.4f} ms (share of the grid {base[stage]:.4f} ms)")
+    return chosen
+
+
 def candidates():
     return [{"grid": g, "tile_cells": c, "tile_threads": t} for g in GRIDS for (c, t) in TILE_SHAPES]
 
@@ -102,7 +158,7 @@ def tune(ctx, prepared, stream, launch="graph", log=None):
         if log:
             log(f"  {shape} {ms:.4f} ms")
     best = min(results, key=lambda r: r[1])
-    ctx.set_tuning(0, 0, 0)
+    set_shape(ctx, {**DEFAULT, "stage_grids": {}})
     return best[0], results
 
 
@@ -149,7 +205,18 @@ def main(argv=None):
         best_ms = min(m for _, m in results)
         log(f"  best {best} {best_ms:.4f} ms (default {default_ms:.4f} ms)")
         if key not in classes or best_ms < classes[key]["ms"]:
-            classes[key] = {**best, "ms": round(best_ms, 5), "default_ms": round(default_ms, 5), "workload": name}
+            grids = tune_stage_grids(ctx, prep, stream, best, log)
+            entry = {**best, "ms": round(best_ms, 5), "default_ms": round(default_ms, 5), "workload": name}
+            if grids:
+                # keep them only if the whole call (graph replay) is faster with them
+                ms_g = min(time_shape(ctx, prep, stream, {**best, "stage_grids": grids}) for _ in range(2))
+                ms_0 = min(time_shape(ctx, prep, stream, {**best, "stage_grids": {}}) for _ in range(2))
+                log(f"  with stage grids {ms_g:.4f} ms, without {ms_0:.4f} ms")
+                if ms_g < ms_0:
+                    entry["stage_grids"] = grids
+                    entry["ms"] = round(ms_g, 5)
+            set_shape(ctx, {**DEFAULT, "stage_grids": {}})
+            classes[key] = entry
     ctx.close()
     with open(args.out, "w") as f:
         json.dump({"device": torch.cuda.get_device_name(0), "classes": classes}, f, indent=1, sort_keys=True)

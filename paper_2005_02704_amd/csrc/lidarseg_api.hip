@@ -86,6 +86,7 @@ struct lidar_ctx {
 
     // tuning
     int grid_wg = 0;      // 0 = automatic
+    int stage_grid[N_STAGES] = {0};  // per stage workgroups of batched and graph launches, 0 = from grid_wg
     int tile_cells = 1024;
     int tile_threads = 256;
 
@@ -270,6 +271,16 @@ int lidar_ctx_set_tuning(lidar_ctx* c, int32_t grid_workgroups, int32_t tile_cel
     c->grid_wg = grid_workgroups;
     c->tile_cells = cells;
     c->tile_threads = threads;
+    c->drop_graph();
+    return LIDAR_OK;
+}
+
+int lidar_ctx_set_stage_grid(lidar_ctx* c, int32_t stage, int32_t workgroups) {
+    if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
+    if (stage < 0 || stage >= N_STAGES) return c->fail(LIDAR_EINVAL, "stage must lie in [0, LIDAR_N_STAGES)");
+    if (workgroups < 0) return c->fail(LIDAR_EINVAL, "workgroups must be >= 0");
+    if (c->stage_grid[stage] == workgroups) return LIDAR_OK;
+    c->stage_grid[stage] = workgroups;
     c->drop_graph();
     return LIDAR_OK;
 }
@@ -697,6 +708,7 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
             cfg.score = any_score;
             cfg.mesh_only = mesh_only;
             cfg.grid = auto_grid;
+            std::copy(c->stage_grid, c->stage_grid + N_STAGES, cfg.stage_grid);
             hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
             e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
             if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
@@ -728,6 +740,7 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
                 cfg.score = any_score;
                 cfg.mesh_only = mesh_only;
                 cfg.grid = auto_grid;
+                std::copy(c->stage_grid, c->stage_grid + N_STAGES, cfg.stage_grid);
                 hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
                 e = hipStreamEndCapture(cap_stream, &c->graph);
                 (void)hipStreamDestroy(cap_stream);

@@ -92,6 +92,8 @@ inline int tile_width(int H, int tile_cells) {
     return tw < 1 ? 1 : tw;
 }
 
+constexpr int N_STAGES = 11;  // bin, count, geom, cc, merge, compress, flatten, scan, label, post, score
+
 struct LaunchCfg {
     int grid;        // workgroups for grid-stride stages
     int tile_cells;  // 512, 1024 or 2048
@@ -104,9 +106,9 @@ struct LaunchCfg {
     bool post = false;   // launch the segment-removal / point-label stage
     bool score = false;  // launch the edge-score stage
     bool mesh_only = false;  // binning, mesh and normals only (no labelling stages)
+    int stage_grid[N_STAGES] = {};  // per stage: workgroups, 0 = from grid
 };
 
-constexpr int N_STAGES = 11;  // bin, count, geom, cc, merge, compress, flatten, scan, label, post, score
 
 // Tile shapes (cells per tile, threads per tile workgroup) the kernels are built for.
 bool tile_shape_supported(int tile_cells, int tile_threads);

@@ -1513,11 +1513,11 @@ __global__ __launch_bounds__(NT) void k_score(const BatchHeader* __restrict__ hd
 
 // The three tile kernels for one tile shape (TT threads, MAXC cells per tile).
 template <int TT, int MAXC>
-void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_tiles, int g_cc, bool mesh_only,
-                        hipStream_t stream, const std::function<void()>& mark) {
-    k_count<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
+void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_count, int g_geom, int g_cc,
+                        bool mesh_only, hipStream_t stream, const std::function<void()>& mark) {
+    k_count<TT, MAXC><<<g_count, TT, 0, stream>>>(d_hdr, ws);
     mark();
-    k_geom<TT, MAXC><<<g_tiles, TT, 0, stream>>>(d_hdr, ws);
+    k_geom<TT, MAXC><<<g_geom, TT, 0, stream>>>(d_hdr, ws);
     mark();
     if (!mesh_only) k_cc<TT, MAXC><<<g_cc, TT, 0, stream>>>(d_hdr, ws);
     mark();
@@ -1533,12 +1533,22 @@ bool tile_shape_supported(int tile_cells, int tile_threads) {
 hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const LaunchCfg& cfg,
                         hipStream_t stream, hipEvent_t* ev) {
     constexpr int NT = 256;
-    const int g_tiles = max(1, min(cfg.grid, cfg.max_tiles));
-    const int g_cc = max(1, min(2 * cfg.grid, cfg.max_tiles));
-    const int g_pblk = max(1, min(cfg.grid, cfg.max_pblk));
-    const int g_vitem = max(1, min(2 * cfg.grid, cfg.max_vitems));
-    const int g_border = max(1, min(2 * cfg.grid, (cfg.max_tiles + NT / 64 - 1) / (NT / 64)));
-    const int g_frames = max(1, min(cfg.grid, cfg.max_frames));
+    // workgroups of a stage: its own setting, else its share of the grid, never
+    // more than it has work items
+    const auto pick = [&](int stage, int dflt, int items) {
+        return max(1, min(cfg.stage_grid[stage] > 0 ? cfg.stage_grid[stage] : dflt, items));
+    };
+    const int border_items = (cfg.max_tiles + NT / 64 - 1) / (NT / 64);
+    const int g_pblk = pick(0, cfg.grid, cfg.max_pblk);
+    const int g_count = pick(1, 2 * cfg.grid, cfg.max_tiles);
+    const int g_tiles = pick(2, cfg.grid, cfg.max_tiles);
+    const int g_cc = pick(3, 2 * cfg.grid, cfg.max_tiles);
+    const int g_merge = pick(4, 2 * cfg.grid, border_items);
+    const int g_compress = pick(5, 2 * cfg.grid, border_items);
+    const int g_vitem = pick(6, 2 * cfg.grid, cfg.max_vitems);
+    const int g_frames = pick(7, cfg.grid, cfg.max_frames);
+    const int g_label = pick(8, 2 * cfg.grid, cfg.max_vitems);
+    const int g_score = pick(10, 2 * cfg.grid, cfg.max_tiles);
     int n = 0;
     hipError_t e = hipSuccess;
     const std::function<void()> mark = [&]() {
@@ -1550,11 +1560,11 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
     mark();
     const int shape = cfg.tile_cells * 4 + cfg.tile_threads / 256;
     switch (shape) {
-        case 512 * 4 + 1: launch_tile_stages<256, 512>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
-        case 2048 * 4 + 1: launch_tile_stages<256, 2048>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
-        case 1024 * 4 + 2: launch_tile_stages<512, 1024>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
-        case 2048 * 4 + 2: launch_tile_stages<512, 2048>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
-        default: launch_tile_stages<256, 1024>(d_hdr, ws, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        case 512 * 4 + 1: launch_tile_stages<256, 512>(d_hdr, ws, g_count, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        case 2048 * 4 + 1: launch_tile_stages<256, 2048>(d_hdr, ws, g_count, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        case 1024 * 4 + 2: launch_tile_stages<512, 1024>(d_hdr, ws, g_count, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        case 2048 * 4 + 2: launch_tile_stages<512, 2048>(d_hdr, ws, g_count, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
+        default: launch_tile_stages<256, 1024>(d_hdr, ws, g_count, g_tiles, g_cc, cfg.mesh_only, stream, mark); break;
     }
     if (cfg.mesh_only) {
         // no labelling: the stage marks stay in place (zero time), and the key
@@ -1570,23 +1580,24 @@ hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const Lau
         const hipError_t le = hipGetLastError();
         return le != hipSuccess ? le : e;
     }
-    k_merge<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);
+    k_merge<NT><<<g_merge, NT, 0, stream>>>(d_hdr, ws);
     mark();
-    k_compress<NT><<<g_border, NT, 0, stream>>>(d_hdr, ws);
+    k_compress<NT><<<g_compress, NT, 0, stream>>>(d_hdr, ws);
     mark();
     k_flatten<NT><<<g_vitem, NT, 0, stream>>>(d_hdr, ws);
     mark();
     k_scan<NT><<<g_frames, NT, 0, stream>>>(d_hdr, ws);
     mark();
-    k_resolve<NT><<<g_vitem, NT, 0, stream>>>(d_hdr, ws);
+    k_resolve<NT><<<g_label, NT, 0, stream>>>(d_hdr, ws);
     mark();
     if (cfg.post) {
         const int64_t items = (int64_t)cfg.max_vitems + cfg.max_pblk;
-        const int g_post = (int)(items < 2 * (int64_t)cfg.grid ? (items > 0 ? items : 1) : 2 * (int64_t)cfg.grid);
+        const int64_t want = cfg.stage_grid[9] > 0 ? cfg.stage_grid[9] : 2 * (int64_t)cfg.grid;
+        const int g_post = (int)(items < want ? (items > 0 ? items : 1) : want);
         k_post<NT><<<g_post, NT, 0, stream>>>(d_hdr, ws);
     }
     mark();
-    if (cfg.score) k_score<NT><<<g_cc, NT, 0, stream>>>(d_hdr, ws);
+    if (cfg.score) k_score<NT><<<g_score, NT, 0, stream>>>(d_hdr, ws);
     mark();
     const hipError_t le = hipGetLastError();
     return le != hipSuccess ? le : e;

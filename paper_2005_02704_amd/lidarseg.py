@@ -32,6 +32,7 @@ LIDAR_PRED_COSINE = 1
 EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lidar_last_error",
            "lidar_query_sizes", "lidar_mesh_segment", "lidar_mesh_normals", "lidar_label_grid",
            "lidar_ctx_set_workspace_limit", "lidar_ctx_workspace_bytes", "lidar_ctx_set_tuning",
+           "lidar_ctx_set_stage_grid",
            "lidar_ctx_set_profiling", "lidar_ctx_stage_times")
 LIDAR_N_STAGES = 11
 STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post", "score")
@@ -104,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     L.lidar_ctx_set_workspace_limit.restype = ctypes.c_int
     L.lidar_ctx_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
     L.lidar_ctx_workspace_bytes.restype = ctypes.c_int
+    L.lidar_ctx_set_stage_grid.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    L.lidar_ctx_set_stage_grid.restype = ctypes.c_int
     L.lidar_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lidar_ctx_set_tuning.restype = ctypes.c_int
     L.lidar_ctx_set_profiling.argtypes = [P, ctypes.c_int32]
@@ -219,6 +222,12 @@ class LidarContext:
     def set_tuning(self, grid_workgroups: int = 0, tile_cells: int = 0, tile_threads: int = 0):
         rc = self._L.lidar_ctx_set_tuning(self._h, int(grid_workgroups), int(tile_cells), int(tile_threads))
         self._check(rc)
+
+    def set_stage_grid(self, stage, workgroups: int = 0):
+        """Workgroups of one stage (name from STAGES, or index) in batched and graph
+        launches; 0 = its share of the tuning grid."""
+        k = STAGES.index(stage) if isinstance(stage, str) else int(stage)
+        self._check(self._L.lidar_ctx_set_stage_grid(self._h, k, int(workgroups)))
 
     def set_profiling(self, enable: bool):
         self._check(self._L.lidar_ctx_set_profiling(self._h, 1 if enable else 0))

@@ -18,7 +18,16 @@ def test_batch_class_buckets():
 
 
 def test_lookup_falls_back_to_the_default():
-    assert autotune.lookup([_geo(7, 333)], table={}) == autotune.DEFAULT
+    assert autotune.lookup([_geo(7, 333)], table={}) == {**autotune.DEFAULT, "stage_grids": {}}
+
+
+def test_lookup_returns_stage_grids():
+    key = autotune.batch_class([_geo(16, 1800)])
+    table = {key: {"grid": 2048, "tile_cells": 512, "tile_threads": 256, "ms": 1.0, "default_ms": 1.0,
+                   "stage_grids": {"bin": 1536, "geom": 6144}}}
+    shape = autotune.lookup([_geo(16, 1800)], table=table)
+    assert shape == {"grid": 2048, "tile_cells": 512, "tile_threads": 256,
+                     "stage_grids": {"bin": 1536, "geom": 6144}}
 
 
 def test_committed_table_holds_supported_shapes():
@@ -29,6 +38,9 @@ def test_committed_table_holds_supported_shapes():
         assert (entry["tile_cells"], entry["tile_threads"]) in shapes, key
         assert entry["grid"] in autotune.GRIDS
         assert entry["ms"] <= entry["default_ms"] + 1e-9
+        from paper_2005_02704_amd.lidarseg import STAGES
+        for stage, g in entry.get("stage_grids", {}).items():
+            assert stage in STAGES and g in autotune.STAGE_GRIDS, (key, stage, g)
     # the benchmark batch has an entry
     assert "H128-W4096-F64" in table
 

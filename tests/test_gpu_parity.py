@@ -95,6 +95,17 @@ def test_launch_forms_and_tiles_agree(ctx):
             for a, b in zip(ref, got):
                 for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
                     assert np.array_equal(a[k], b[k]), (grid, tc, th, launch, k)
+    # every stage at its own workgroup count (including one workgroup)
+    ctx.set_tuning(2048, 1024, 256)
+    for k, stage in enumerate(("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label")):
+        ctx.set_stage_grid(stage, (1, 7, 1536, 6144, 3, 8192, 5, 1, 700)[k])
+    for launch in ("batched", "graph"):
+        got = run_gpu(ctx, items, launch=launch)
+        for a, b in zip(ref, got):
+            for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
+                assert np.array_equal(a[k], b[k]), ("stage grids", launch, k)
+    for stage in ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label"):
+        ctx.set_stage_grid(stage, 0)
     ctx.set_tuning(0, 0, 0)
     for f, g in zip(frames, ref):
         r = run_oracle(f.xyz, f.sensor, 1)
@@ -140,4 +151,4 @@ def test_benchmark_batch_in_its_launch_configuration(ctx):
         for k in (0, 21, 42, 63):
             assert sandwich(got[k]["labels"], frames[k].xyz, frames[k].sensor, 1), k
     finally:
-        ctx.set_tuning(0, 0, 0)
+        autotune.set_shape(ctx, {**autotune.DEFAULT, "stage_grids": {}})
