@@ -180,6 +180,13 @@ def test_call_arguments_are_rejected_before_any_work(ctx):
     bad_geo = lp.SensorGeometry(f.sensor.elevations()[::-1].copy(), f.sensor.n_azimuth, 1)
     with pytest.raises(lp.LidarError):
         call(inputs=[(x, bad_geo, None)], outs=[lp.Outputs(geo, dev)])
+    # tuning arguments
+    for args in ((-1, 0, 0), (0, 768, 256), (0, 512, 512)):
+        with pytest.raises(lp.LidarError):
+            ctx.set_tuning(*args)
+    for stage, wg in ((-1, 4), (lp.LIDAR_N_STAGES, 4), (0, -3)):
+        with pytest.raises(lp.LidarError):
+            ctx.set_stage_grid(stage, wg)
     # and the context still works
     g = run_gpu(ctx, [(f.xyz, f.sensor, 1, 1, None)], launch="batched")[0]
     r = run_oracle(f.xyz, f.sensor, 1)
