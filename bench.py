@@ -6,7 +6,7 @@ One step = the full path over the batch (64 street sweeps; rings drawn from
 {16,32,64,128}, azimuth widths from {1024,2048,4096}; range noise 1 cm; 10%
 dropouts; per-frame seeds), as one library call.  The batch is timed in every
 launch form: the batched chain replayed from a captured hipGraph, launched
-directly, launched directly with three batches in flight (three contexts and
+directly, launched directly with two batches in flight (two contexts and
 streams taken in turn, each call still a whole pass over the batch), and as
 plain per-frame chains.  `value` is points/s of the fastest form that serves
 whole batches (`config.launch` names it).  The dominant kernel is timed with
@@ -186,7 +186,7 @@ def main():
                     help="launch form of the served run's groups")
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
-    ap.add_argument("--in-flight", type=int, default=3,
+    ap.add_argument("--in-flight", type=int, default=2,
                     help="also time the batched form with this many batches in flight (1 = skip)")
     ap.add_argument("--forms", default="graph,batched,plain",
                     help="launch forms to time (graph is always timed: it gives value)")
