@@ -87,7 +87,7 @@ def served_run(args, lp, synth, torch):
     # warm the slots (workspace growth, graph capture) before timing
     warm = Server(ex, budget_bytes=budget, max_batch=16)
     warm.run_schedule([(0.0, q, 0) for q in range(8)] * 3, make)
-    srv = Server(ex, budget_bytes=budget, max_batch=16)
+    srv = Server(ex, budget_bytes=budget, max_batch=16, timeout_s=1.0)
     sched = poisson_schedule([r for _, r in sensors], args.served_seconds, seed=args.seed, n_payloads=n_pool)
     log(f"served: {len(sched)} sweeps over {args.served_seconds:.0f}s")
     wall = srv.run_schedule(sched, make)
@@ -99,10 +99,11 @@ def served_run(args, lp, synth, torch):
     stc = cap.stats(wall_c)
     log(f"  capacity: {stc['points_per_s']:.3e} points/s ({stc['requests']} sweeps at once)")
     ex.close()
-    keep = ("requests", "points_per_s", "p50_ms", "p99_ms", "max_ms", "mean_batch", "max_slots_in_flight",
-            "peak_device_bytes")
+    keep = ("requests", "failed", "points_per_s", "p50_ms", "p99_ms", "max_ms", "mean_batch",
+            "max_slots_in_flight", "peak_device_bytes")
     return {"workload": "8 sensors, rings 16/32/64/128, azimuth 1024/2048/4096, 10-20 Hz Poisson, "
-                        f"{args.served_seconds:.0f}s, budget 1 GiB, 3 slots, {args.served_launch} launches",
+                        f"{args.served_seconds:.0f}s, budget 1 GiB, 3 slots, {args.served_launch} launches, "
+                        "1 s watchdog per group",
             **{k: (round(st[k], 3) if isinstance(st[k], float) else st[k]) for k in keep},
             "latency": "host arrival to labels/vertex_point/counts in pinned host memory",
             "capacity_points_per_s": round(stc["points_per_s"], 1),

@@ -35,6 +35,7 @@ class Request:
     batch_id: int = -1
     batch_size: int = 0
     result: dict | None = None
+    failed: str = ""       # why the request failed (empty: served)
 
     @property
     def latency(self) -> float:
@@ -47,6 +48,8 @@ class SlotState:
     handle: object = None
     batch: list = field(default_factory=list)
     bytes_held: int = 0
+    t_submit: float = 0.0
+    abandoned: bool = False  # its tickets failed on the watchdog; the device work still runs
 
 
 class Server:
@@ -58,12 +61,20 @@ class Server:
       submit(slot, reqs) -> handle  enqueue the group; returns at once
       poll(handle) -> bool          True once the group's outputs are on the host
       results(handle) -> list       per-request result dicts (after poll is True)
+
+    timeout_s: a watchdog on each group.  A group still running that long after
+    submission fails its requests (failed = "timeout"; they are finished and
+    counted, without results), so callers are never left waiting.  Its slot and
+    memory stay held until the device work really completes (the work may
+    still write into them), and are then released silently.
     """
 
-    def __init__(self, executor, budget_bytes: int, max_batch: int = 64):
+    def __init__(self, executor, budget_bytes: int, max_batch: int = 64, timeout_s: float | None = None):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
+        self.timeout_s = timeout_s
+        self.failed = 0
         self.slots = [SlotState() for _ in range(executor.n_slots)]
         self.waiting: collections.deque = collections.deque()
         self.in_use = 0
@@ -102,6 +113,7 @@ class Server:
                 r.batch_size = len(group)
             self.batches += 1
             st.busy, st.batch, st.bytes_held = True, group, held
+            st.t_submit, st.abandoned = now, False
             self.in_use += held
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             st.handle = self.ex.submit(s, group)
@@ -109,21 +121,35 @@ class Server:
 
     def _complete(self):
         for st in self.slots:
-            if st.busy and self.ex.poll(st.handle):
+            if not st.busy:
+                continue
+            if self.ex.poll(st.handle):
                 now = time.perf_counter()
-                for r, res in zip(st.batch, self.ex.results(st.handle)):
-                    r.t_done = now
-                    r.result = res
-                    self.done.append(r)
+                if not st.abandoned:
+                    for r, res in zip(st.batch, self.ex.results(st.handle)):
+                        r.t_done = now
+                        r.result = res
+                        self.done.append(r)
                 self.in_use -= st.bytes_held
-                st.busy, st.batch, st.handle, st.bytes_held = False, [], None, 0
+                st.busy, st.batch, st.handle, st.bytes_held, st.abandoned = False, [], None, 0, False
+            elif (self.timeout_s is not None and not st.abandoned
+                  and time.perf_counter() - st.t_submit > self.timeout_s):
+                now = time.perf_counter()
+                for r in st.batch:
+                    r.t_done = now
+                    r.failed = "timeout"
+                    self.done.append(r)
+                self.failed += len(st.batch)
+                st.abandoned = True
 
     def step(self):
         self._complete()
         self._admit(time.perf_counter())
 
     def idle(self) -> bool:
-        return not self.waiting and not any(st.busy for st in self.slots)
+        """Nothing waiting and no request in flight (an abandoned slot's device
+        work may still be running; its requests are already finished)."""
+        return not self.waiting and not any(st.busy and not st.abandoned for st in self.slots)
 
     # -- driving a timed arrival schedule -----------------------------------
     def run_schedule(self, schedule, make_request, poll_sleep: float = 5e-5):
@@ -150,10 +176,12 @@ class Server:
 
     # -- statistics ----------------------------------------------------------
     def stats(self, wall_s: float):
-        lat = np.array([r.latency for r in self.done]) * 1e3
-        pts = sum(r.n_points for r in self.done)
+        served = [r for r in self.done if not r.failed]
+        lat = np.array([r.latency for r in served]) * 1e3
+        pts = sum(r.n_points for r in served)
         return {
-            "requests": len(self.done),
+            "requests": len(served),
+            "failed": self.failed,
             "points": int(pts),
             "points_per_s": pts / wall_s if wall_s > 0 else 0.0,
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,

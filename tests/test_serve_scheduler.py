@@ -114,3 +114,47 @@ def test_poisson_schedule_rates():
     n1 = sum(1 for t, s, _ in sched if s == 1)
     assert 480 < n0 < 720 and 1020 < n1 < 1380
     assert all(a[0] <= b[0] for a, b in zip(sched, sched[1:]))
+
+
+class StuckExecutor(FakeExecutor):
+    """Like FakeExecutor, but the groups that hold request `stuck` complete only
+    when `release` is set: a device that stopped making progress."""
+
+    def __init__(self, n_slots, delay, sensors, stuck):
+        super().__init__(n_slots, delay, sensors)
+        self.stuck = stuck
+        self.release = False
+
+    def poll(self, h):
+        if any(r.rid == self.stuck for r in h["reqs"]) and not self.release:
+            return False
+        return super().poll(h)
+
+
+def test_watchdog_fails_a_stuck_group_and_keeps_its_slot(frames):
+    sens, fr = frames
+    ex = StuckExecutor(n_slots=2, delay=0.005, sensors=sens, stuck=0)
+    srv = Server(ex, budget_bytes=10**9, max_batch=1, timeout_s=0.05)
+    make = _make(frames)
+    for rid in range(6):
+        srv.submit(make(rid, rid % 2, rid % 3, time.perf_counter()))
+    t0 = time.perf_counter()
+    while not srv.idle() and time.perf_counter() - t0 < 5.0:
+        srv.step()
+        time.sleep(1e-3)
+    assert srv.idle()
+    done = {r.rid: r for r in srv.done}
+    assert sorted(done) == list(range(6))
+    assert done[0].failed == "timeout" and done[0].result is None
+    assert 0.05 <= done[0].latency < 1.0
+    assert all(not done[k].failed and done[k].result is not None for k in range(1, 6))
+    assert srv.failed == 1 and srv.stats(1.0)["failed"] == 1 and srv.stats(1.0)["requests"] == 5
+    # the stuck group's slot was never reused: every other group ran on the other slot
+    stuck_slot = done[0].slot
+    assert all(done[k].slot != stuck_slot for k in range(1, 6))
+    # its memory is released only when the device work completes
+    assert srv.in_use == ex.bytes_for(done[0])
+    ex.release = True
+    srv.step()
+    assert srv.in_use == 0 and not any(st.busy for st in srv.slots)
+    assert len(srv.done) == 6   # the late completion adds no second result
