@@ -157,6 +157,15 @@ def accuracy_run(args, lp, synth, torch, ctx, frames, geos, stream):
             "batch": batch, "paper_shape_32x1800": paper, "paper_shape_environments": n_env}
 
 
+def rocm_version():
+    """The ROCm release the library was built against, as installed."""
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            return f.read().strip()
+    except OSError:
+        return "unknown"
+
+
 def cpu_model():
     """The host CPU's model name, as the kernel reports it."""
     try:
@@ -409,7 +418,8 @@ def main():
                                f"azimuth 1024/2048/4096, s=1)", "frames": args.frames,
                    "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
                    "launch": best, "seed": args.seed, "launch_shape": forms[best]["launch_shape"],
-                   "launch_shape_source": shape_src},
+                   "launch_shape_source": shape_src, "rocm": rocm_version(),
+                   "device": torch.cuda.get_device_name(0)},
         "forms": forms,
         "vertices_per_s": round(V / (ms_best * 1e-3), 1),
         "path_algorithmic_gbs": round(path_gbs, 1),
