@@ -2,6 +2,7 @@
 // tables, launch forms (plain per-frame chains, one batched chain, or a captured
 // hipGraph of the batched chain).  The C ABI is declared in include/lidarseg.h.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -333,9 +334,18 @@ namespace {
 
 enum CallMode { CALL_SEGMENT = 0, CALL_MESH_ONLY = 1, CALL_LABEL_GRID = 2 };
 
+// One roctx range per library call (named by entry point), visible to
+// rocprofv3 --marker-trace; without a tool attached the calls do nothing.
+struct CallRange {
+    explicit CallRange(const char* name) { roctxRangePushA(name); }
+    ~CallRange() { roctxRangePop(); }
+};
+
 int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const lidar_params_t* params,
               lidar_result_t* results, void* stream_, int32_t launch, CallMode mode) {
     if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
+    const CallRange range(mode == CALL_MESH_ONLY ? "lidar_mesh_normals"
+                          : mode == CALL_LABEL_GRID ? "lidar_label_grid" : "lidar_mesh_segment");
     const bool mesh_only = mode == CALL_MESH_ONLY;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     if (n_frames < 1 || !frames || !results) return c->fail(LIDAR_EINVAL, "need n_frames >= 1 frames and results");
