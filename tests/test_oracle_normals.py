@@ -8,7 +8,10 @@ What geometry fixes:
   * every triangle normal satisfies N . p > 0 (lattice orientation), so every
     vertex normal does too;
   * a closed form for mutually orthogonal edge vectors pins the pairing and the
-    1/(|V_t| + |V_t+1|) weighting (tests/golden/normal_weighting.json).
+    1/(|V_t| + |V_t+1|) weighting (tests/golden/normal_weighting.json);
+  * a closed form for a full six-neighbour star with axis-aligned edges of
+    distinct lengths (also rotated exactly) pins all six pairs, their cyclic
+    order, the closing pair F x A and the weight of each.
 """
 import json
 import math
@@ -56,6 +59,53 @@ def test_weighting_closed_form():
         n, h = oracle.normals(H, Wp, 0, xyz, valid)
         assert h[cell(0, 1)] == 1
         np.testing.assert_allclose(n[cell(0, 1)], case["expected_normal"], rtol=0, atol=1e-15)
+
+
+SIX_LENGTHS = [(1, 2, 3, 4, 5, 6), (6, 1, 5, 2, 4, 3), (1, 1, 1, 1, 1, 1), (2, 7, 1, 8, 2, 8)]
+# Rotations with rational entries (3-4-5 about z, 5-12-13 about x), so that
+# lattice coordinates that are multiples of 65 stay integers after rotation.
+ROT_Z = np.array([[3, -4, 0], [4, 3, 0], [0, 0, 5]], np.float64) / 5.0
+ROT_X = np.array([[13, 0, 0], [0, 5, -12], [0, 12, 5]], np.float64) / 13.0
+
+
+@pytest.mark.parametrize("lengths", SIX_LENGTHS)
+@pytest.mark.parametrize("rot", ["none", "z", "xz"])
+def test_weighting_closed_form_all_six_pairs(lengths, rot):
+    # Anchor p at ring 1, column 1 of a 3 x 3 open lattice with all six
+    # neighbours, named in the anticlockwise order of Section 2: A = (2,1),
+    # B = (2,2), C = (1,2), D = (0,1), E = (0,0), F = (1,0) (ring, column).
+    # With V_A = a e1, V_B = b e2, V_C = c e3, V_D = -d e1, V_E = -e e2,
+    # V_F = -f e3 the six consecutive products are
+    #   A x B = ab e3, B x C = bc e1, C x D = -cd e2,
+    #   D x E = de e3, E x F = ef e1, F x A = -fa e2,
+    # so the weighted sum is
+    #   (bc/(b+c) + ef/(e+f), -(cd/(c+d) + fa/(f+a)), ab/(a+b) + de/(d+e)).
+    # A proper rotation R of every edge rotates each product and keeps every
+    # length, so the normal of the rotated star is R n.  Every pair, its order,
+    # its sign and its weight enter one component; dropping the closing pair
+    # F x A, permuting the neighbours or changing the weight moves the result
+    # far beyond the tolerance.
+    a, b, c, d, e, f = (65.0 * x for x in lengths)
+    s = np.array([b * c / (b + c) + e * f / (e + f),
+                  -(c * d / (c + d) + f * a / (f + a)),
+                  a * b / (a + b) + d * e / (d + e)])
+    R = {"none": np.eye(3), "z": ROT_Z, "xz": ROT_X @ ROT_Z}[rot]
+    expected = R @ (s / np.linalg.norm(s))
+    p = np.array([1300.0, -650.0, 390.0])
+    H, Wp = 3, 3
+    cell = lambda i, k: k * H + i  # noqa: E731
+    xyz = np.zeros((H * Wp, 3), np.float32)
+    valid = np.zeros(H * Wp, np.uint8)
+    star = [((1, 1), [0, 0, 0]), ((2, 1), [a, 0, 0]), ((2, 2), [0, b, 0]), ((1, 2), [0, 0, c]),
+            ((0, 1), [-d, 0, 0]), ((0, 0), [0, -e, 0]), ((1, 0), [0, 0, -f])]
+    for (i, k), v in star:
+        q = p + R @ np.array(v, np.float64)
+        assert np.all(q == np.round(q)) and np.all(np.abs(q) < 2 ** 24)  # exact in FP32
+        xyz[cell(i, k)] = q
+        valid[cell(i, k)] = 1
+    n, h = oracle.normals(H, Wp, 0, xyz, valid)
+    assert h[cell(1, 1)] == 1
+    np.testing.assert_allclose(n[cell(1, 1)], expected, rtol=0, atol=1e-14)
 
 
 def test_noise_free_ground_normals_are_exact():
