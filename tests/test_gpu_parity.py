@@ -85,8 +85,8 @@ def test_launch_forms_and_tiles_agree(ctx):
             for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
                 assert np.array_equal(a[k], b[k]), (launch, k)
             assert a["counts"] == b["counts"]
-    # grids below and above the number of tile counters of the mesh stage, and a
-    # single workgroup per stage (every look-back then finds its tiles done)
+    # every tile shape, grids from one workgroup (one workgroup walks every tile
+    # of every stage) to more workgroups than the batch has tiles
     for grid, tc, th in ((0, 512, 256), (0, 2048, 256), (0, 1024, 512), (0, 2048, 512), (300, 1024, 256),
                          (4096, 1024, 256), (16, 1024, 256), (1, 2048, 512)):
         ctx.set_tuning(grid, tc, th)
