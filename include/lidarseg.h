@@ -197,13 +197,15 @@ int lidar_ctx_workspace_bytes(const lidar_ctx* ctx, uint64_t* held_bytes);
  * stage (0 = automatic: 4 per compute unit), the largest tile in lattice cells
  * and the threads of a tile workgroup.  Supported tile shapes (cells, threads):
  * (512, 256), (1024, 256), (2048, 256), (1024, 512), (2048, 512); 0 selects
- * 1024 cells or 256 threads.  Results do not depend on the shape. */
+ * 1024 cells or 256 threads.  Results do not depend on the shape.  A change
+ * of shape drops the captured graph, after waiting for this context's earlier
+ * graph replays to finish (a host wait). */
 int lidar_ctx_set_tuning(lidar_ctx* ctx, int32_t grid_workgroups, int32_t tile_cells, int32_t tile_threads);
 
 /* Workgroups of one stage (index in the order of the stage list below) in
  * batched and graph launches of later calls, in place of its share of the
  * grid set by lidar_ctx_set_tuning; 0 restores that share.  Results do not
- * depend on it. */
+ * depend on it.  A change waits and drops the graph as lidar_ctx_set_tuning. */
 int lidar_ctx_set_stage_grid(lidar_ctx* ctx, int32_t stage, int32_t workgroups);
 
 /* Per-stage timing of plain and batched launches (not of graph replays), with

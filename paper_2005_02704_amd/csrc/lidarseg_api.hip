@@ -269,6 +269,10 @@ int lidar_ctx_set_tuning(lidar_ctx* c, int32_t grid_workgroups, int32_t tile_cel
         return c->fail(LIDAR_EINVAL, "unsupported tile shape (cells, threads): use (512|1024|2048, 256) "
                                      "or (1024|2048, 512)");
     if (c->grid_wg == grid_workgroups && c->tile_cells == cells && c->tile_threads == threads) return LIDAR_OK;
+    // a replay of the captured chain may still run: wait for this context's
+    // earlier calls before the graph is destroyed
+    const int rc = c->wait_idle();
+    if (rc) return rc;
     c->grid_wg = grid_workgroups;
     c->tile_cells = cells;
     c->tile_threads = threads;
@@ -281,6 +285,8 @@ int lidar_ctx_set_stage_grid(lidar_ctx* c, int32_t stage, int32_t workgroups) {
     if (stage < 0 || stage >= N_STAGES) return c->fail(LIDAR_EINVAL, "stage must lie in [0, LIDAR_N_STAGES)");
     if (workgroups < 0) return c->fail(LIDAR_EINVAL, "workgroups must be >= 0");
     if (c->stage_grid[stage] == workgroups) return LIDAR_OK;
+    const int rc = c->wait_idle();  // as in lidar_ctx_set_tuning
+    if (rc) return rc;
     c->stage_grid[stage] = workgroups;
     c->drop_graph();
     return LIDAR_OK;
