@@ -419,7 +419,9 @@ def main():
                    "points_per_step": N, "vertices_per_step": V, "triangles_per_step": T,
                    "launch": best, "seed": args.seed, "launch_shape": forms[best]["launch_shape"],
                    "launch_shape_source": shape_src, "rocm": rocm_version(),
-                   "device": torch.cuda.get_device_name(0)},
+                   "device": torch.cuda.get_device_name(0),
+                   "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", ""),
+                   "compute_units": torch.cuda.get_device_properties(0).multi_processor_count},
         "forms": forms,
         "vertices_per_s": round(V / (ms_best * 1e-3), 1),
         "path_algorithmic_gbs": round(path_gbs, 1),
