@@ -128,6 +128,37 @@ def test_graph_replays_follow_new_content(ctx):
             assert np.array_equal(x["normals"], y["normals"])
 
 
+def test_tuning_changes_between_unsynchronised_graph_calls(ctx):
+    """Graph calls enqueued without a host wait, each followed by a new launch
+    shape and stage grid: the setters wait for the replays still running before
+    they drop the captured graph, and every call's outputs stay those of the
+    batched form."""
+    import torch
+    import paper_2005_02704_amd as lp
+    from gpu_helpers import geometry
+    frames = synth.batch_frames(8, 31)
+    ref = run_gpu(ctx, [(f.xyz, f.sensor, 1, 1, None) for f in frames], launch="batched")
+    inputs = [(torch.from_numpy(f.xyz).cuda(), geometry(f.sensor), None) for f in frames]
+    params = lp.make_params()
+    calls = []
+    try:
+        for shape, geom in (((2048, 2048, 512), 777), ((300, 512, 256), 0), ((0, 1024, 512), 4096)):
+            calls.append(lp.lidar_mesh_segment(ctx, inputs, params, launch="graph"))
+            ctx.set_tuning(*shape)
+            ctx.set_stage_grid("geom", geom)
+        calls.append(lp.lidar_mesh_segment(ctx, inputs, params, launch="graph"))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_stage_grid("geom", 0)
+        ctx.set_tuning(0, 0, 0)
+    for n, outs in enumerate(calls):
+        for o, r in zip(outs, ref):
+            t = o.trimmed()
+            assert t["counts"] == r["counts"], n
+            for k in ("vertices", "normals", "labels", "triangles", "vertex_point"):
+                assert np.array_equal(t[k].cpu().numpy(), r[k]), (n, k)
+
+
 def test_benchmark_batch_in_its_launch_configuration(ctx):
     """The workload bench.py times (64 uneven street sweeps, seed 2024), in the
     graph form with the autotuned launch shape: every frame's geometry against
