@@ -79,6 +79,30 @@ def test_ragged_tiles_and_odd_ring_counts(ctx, H, W):
     assert np.array_equal(nin_g["labels"], r.labels)
 
 
+def test_widest_sweep_at_the_most_rings(ctx):
+    """One sweep of 128 rings x 65 536 firings (8.4 M cells, 4 096 tiles of 2 048
+    cells, one frame): index arithmetic past 2^24 points and cells, the longest
+    sums over earlier tiles, in the batched and graph forms and at the largest
+    tile shape.  Geometry against the oracle, labels bit-exact on the oracle's
+    normals, and the labels of the GPU's own normals between the oracle's
+    thr -/+ 1e-4 partitions."""
+    from gpu_helpers import sandwich
+    sen = synth.Sensor.standard(128, 65536)
+    f = synth.make_frame(sen, "street", 5, sigma=0.01, dropout=0.1)
+    print(f"widest sweep: {f.n_points} points", flush=True)
+    r = run_oracle(f.xyz, sen, 1, 1)
+    ctx.set_tuning(0, 2048, 512)
+    try:
+        g = run_gpu(ctx, [(f.xyz, sen, 1, 1, None)], launch="graph")[0]
+        check_geometry(g, r)
+        assert sandwich(g["labels"], f.xyz, sen, 1)
+        on_ref = run_gpu(ctx, [(f.xyz, sen, 1, 1, r.normals)], launch="batched")[0]
+        assert on_ref["counts"] == tuple(int(v) for v in r.counts)
+        assert np.array_equal(on_ref["labels"], r.labels)
+    finally:
+        ctx.set_tuning(0, 0, 0)
+
+
 def test_open_sweep_without_seam(ctx):
     f = synth.workload_frames("c2_64x2048")[0]
     r = run_oracle(f.xyz, f.sensor, 2, 0)
