@@ -4,6 +4,12 @@ in profiles/ (and the traffic JSON bench.py reads).
 Usage:
   python -m paper_2005_02704_amd.rocprof_summary --trace DIR [--fetch DIR --write DIR]
          --command "the rocprofv3 command" --out profiles/NAME.txt [--traffic-json FILE]
+  python -m paper_2005_02704_amd.rocprof_summary --sq DIR [DIR ...]
+         --command "the rocprofv3 commands" --out profiles/NAME.txt
+
+--sq takes the output folders of --pmc runs of SQ counters (any counters, one
+value per dispatch) and writes their average per dispatch by kernel, with the
+busy ratios and per-wave counts that follow from them.
 
 The profiled run launches only the batched chain (bench.py --forms graph).
 HBM bytes are FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the
@@ -79,9 +85,58 @@ def counter_summary(d: str):
     return by, [v for g, v in copies if g == gmax]
 
 
+def sq_summary(dirs):
+    """Average per dispatch of every counter, by library kernel."""
+    tot = collections.defaultdict(lambda: collections.defaultdict(float))
+    cnt = collections.defaultdict(collections.Counter)
+    for d in dirs:
+        for r in _csv(d, "counter_collection.csv"):
+            k = kname(r["Kernel_Name"])
+            if not k.startswith("k_"):
+                continue
+            tot[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            cnt[k][r["Counter_Name"]] += 1
+    return {k: {c: v / cnt[k][c] for c, v in d.items()} for k, d in tot.items()}
+
+
+# (label, numerator, denominator).  SQ_ACTIVE_INST_* count quad-cycles summed
+# over the SIMDs, SQ_BUSY_CU_CYCLES cycles summed over the compute units: with
+# four SIMDs per compute unit the busy ratios are the fraction of a busy
+# compute unit's cycles in which one SIMD issues that kind of instruction.
+SQ_RATIOS = [
+    ("VALU busy", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CU_CYCLES"),
+    ("scalar busy", "SQ_ACTIVE_INST_SCA", "SQ_BUSY_CU_CYCLES"),
+    ("LDS busy", "SQ_ACTIVE_INST_LDS", "SQ_BUSY_CU_CYCLES"),
+    ("VALU instructions per wave", "SQ_INSTS_VALU", "SQ_WAVES"),
+    ("scalar instructions per wave", "SQ_INSTS_SALU", "SQ_WAVES"),
+    ("LDS instructions per wave", "SQ_INSTS_LDS", "SQ_WAVES"),
+    ("vector memory reads per wave", "SQ_INSTS_VMEM_RD", "SQ_WAVES"),
+    ("vector memory writes per wave", "SQ_INSTS_VMEM_WR", "SQ_WAVES"),
+    ("wave cycles waiting on a dependency", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"),
+    ("wave cycles waiting (any)", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES"),
+]
+
+
+def sq_lines(by):
+    out = []
+    kernels = sorted(by, key=lambda k: -by[k].get("SQ_BUSY_CU_CYCLES", 0.0))
+    counters = sorted({c for d in by.values() for c in d})
+    out.append("counter (average per dispatch)   " + " ".join(f"{k:>13}" for k in kernels))
+    for c in counters:
+        out.append(f"{c:<32} " + " ".join(f"{by[k].get(c, float('nan')):13.4g}" for k in kernels))
+    out += ["", "ratio (numerator / denominator)  " + " ".join(f"{k:>13}" for k in kernels)]
+    for label, num, den in SQ_RATIOS:
+        if not any(num in by[k] and by[k].get(den) for k in kernels):
+            continue
+        vals = [by[k][num] / by[k][den] if num in by[k] and by[k].get(den) else float("nan") for k in kernels]
+        out.append(f"{label:<32} " + " ".join(f"{v:13.4g}" for v in vals) + f"   [{num} / {den}]")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
+    ap.add_argument("--trace")
+    ap.add_argument("--sq", nargs="+", help="output folders of --pmc runs of SQ counters")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--copy-mib", type=int, default=512)
@@ -94,6 +149,16 @@ def main():
     ap.add_argument("--alg-bytes", type=float, default=0.0,
                     help="algorithmic bytes per launch of --kernel (from bench.py's roofline)")
     a = ap.parse_args()
+    if a.sq:
+        lines = ["# rocprofv3 SQ counters of the batched chain, bench.py workload",
+                 f"kernel source hash: {kernel_source_hash()}", f"command: {a.command}", ""]
+        lines += sq_lines(sq_summary(a.sq))
+        with open(a.out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
+    if not a.trace:
+        ap.error("--trace or --sq is required")
     lines = [f"# rocprofv3 summary: {a.kernel} and the rest of the chain, bench.py workload",
              f"command: {a.command}", ""]
     tr = trace_summary(a.trace)
