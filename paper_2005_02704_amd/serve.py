@@ -212,10 +212,12 @@ def poisson_schedule(rates_hz, seconds: float, seed: int, n_payloads: int):
 class GpuExecutor:
     """Slots = lidar contexts with their own streams; resident per-sensor buffers.
 
-    Each sensor owns a small ring of buffer sets (device points, device outputs,
-    pinned host copies of labels / vertex_point / counts).  A group is one
-    batched call on its slot's stream: H2D of the points, the chain, D2H of the
-    segmentation, then an event the scheduler polls."""
+    Each sensor owns a pool of buffer sets (device points, device outputs,
+    pinned host copies of labels / vertex_point / counts): sets_per_sensor are
+    made up front, more when that many of the sensor's sweeps are in flight at
+    once; a set returns to its pool when its results are read and is kept until
+    close.  A group is one batched call on its slot's stream: H2D of the points,
+    the chain, D2H of the segmentation, then an event the scheduler polls."""
 
     def __init__(self, geometries, n_slots: int = 3, device: int = 0, launch: str = "batched",
                  params=None, sets_per_sensor: int = 4, copy_mesh: bool = False):
@@ -234,18 +236,27 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(n_slots)]
         self.sets = [[] for _ in geometries]          # resident buffer sets per sensor
         self.free_sets = [[] for _ in geometries]
-        self.sets_per_sensor = sets_per_sensor
         self.caps = [lp.lidar_query_sizes(g) for g in geometries]
+        for q in range(len(geometries)):
+            for _ in range(sets_per_sensor):
+                self.free_sets[q].append(self._new_set(q))
 
     def bytes_for(self, req) -> int:
         V, T = self.caps[req.sensor]
         g = self.geos[req.sensor]
+        if req.n_points > g.n_rings * g.n_azimuth:
+            # the resident point buffer holds one return per ray
+            raise ValueError(f"request {req.rid}: {req.n_points} points, more than the sensor's "
+                             f"{g.n_rings * g.n_azimuth} rays")
         cells = g.n_rings * g.n_cols
         return 12 * g.n_rings * g.n_azimuth + 36 * V + 12 * T + 8 * cells + 16 * V
 
     def _buffer_set(self, sensor):
         if self.free_sets[sensor]:
             return self.free_sets[sensor].pop()
+        return self._new_set(sensor)
+
+    def _new_set(self, sensor):
         torch = self.torch
         g = self.geos[sensor]
         V, T = self.caps[sensor]
@@ -297,7 +308,7 @@ class GpuExecutor:
     def results(self, h):
         out = []
         for r, bs in zip(h["reqs"], h["sets"]):
-            V, T, K = (int(x) for x in bs["h_counts"])
+            V, T, K = bs["h_counts"].tolist()
             res = dict(counts=(V, T, K), labels=bs["h_labels"][:V].numpy().copy(),
                        vertex_point=bs["h_vpoint"][:V].numpy().copy())
             if self.copy_mesh:

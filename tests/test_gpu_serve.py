@@ -42,6 +42,10 @@ def test_served_mix_equals_alone():
             o = lp.lidar_mesh_segment(ctx, [(x, geos[s], None)], launch="plain")[0].trimmed()
             alone[(s, k)] = {key: (v.cpu().numpy() if hasattr(v, "cpu") else v) for key, v in o.items()}
     ctx.close()
+    # a sweep with more points than the sensor has rays is refused at submission
+    rays = geos[0].n_rings * geos[0].n_azimuth
+    with pytest.raises(ValueError):
+        srv.submit(Request(10 ** 6, 0, pinned[0][0], rays + 1, 0.0))
     ex.close()
     for r in srv.done:
         k = [id(t) for t in pinned[r.sensor]].index(id(r.xyz))
