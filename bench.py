@@ -69,7 +69,8 @@ def stage_bytes(stage, N, V, T):
 def served_run(args, lp, synth, torch):
     """8 simulated sensors (rings 16/32/64/128, widths 1024/2048/4096, 10-20 Hz
     Poisson arrivals) through the continuous-batching server; then the same pool
-    with every request arriving at once (capacity)."""
+    with every request arriving at once (capacity), served in groups and, for
+    comparison, one sweep per call with plain per-frame launches."""
     from paper_2005_02704_amd.serve import GpuExecutor, Request, Server, poisson_schedule
     sensors = synth.served_sensors(8)
     n_pool = 3
@@ -102,6 +103,13 @@ def served_run(args, lp, synth, torch):
     stc = cap.stats(wall_c)
     log(f"  capacity: {stc['points_per_s']:.3e} points/s ({stc['requests']} sweeps at once)")
     ex.close()
+    # the same burst served one sweep per call with plain per-frame launches
+    ex_p = GpuExecutor(geos, n_slots=3, launch="plain")
+    Server(ex_p, budget_bytes=budget, max_batch=1).run_schedule(burst, make)
+    cap_p = Server(ex_p, budget_bytes=budget, max_batch=1)
+    stp = cap_p.stats(cap_p.run_schedule(burst, make))
+    log(f"  capacity, one sweep per plain call: {stp['points_per_s']:.3e} points/s")
+    ex_p.close()
     keep = ("requests", "failed", "points_per_s", "p50_ms", "p99_ms", "max_ms", "mean_batch",
             "max_slots_in_flight", "peak_device_bytes")
     return {"workload": "8 sensors, rings 16/32/64/128, azimuth 1024/2048/4096, 10-20 Hz Poisson, "
@@ -110,7 +118,8 @@ def served_run(args, lp, synth, torch):
             **{k: (round(st[k], 3) if isinstance(st[k], float) else st[k]) for k in keep},
             "latency": "host arrival to labels/vertex_point/counts in pinned host memory",
             "capacity_points_per_s": round(stc["points_per_s"], 1),
-            "capacity_mean_batch": round(stc["mean_batch"], 2)}
+            "capacity_mean_batch": round(stc["mean_batch"], 2),
+            "capacity_plain_one_sweep_per_call_points_per_s": round(stp["points_per_s"], 1)}
 
 
 def mean_scores(outs, lp):

@@ -260,12 +260,19 @@ class GpuExecutor:
         torch = self.torch
         g = self.geos[sensor]
         V, T = self.caps[sensor]
+        Vc = max(V, 1)
+        # counts (3 x int64), labels and vertex_point share one device block and
+        # one pinned block, so that a sweep's segmentation comes back in one copy:
+        # int32 words [0, 6) counts, [8, 8 + Vc) labels, [8 + Vc, 8 + 2 Vc) vertex_point
+        d_block = torch.zeros(8 + 2 * Vc, dtype=torch.int32, device=self.dev)
+        h_block = torch.empty(8 + 2 * Vc, dtype=torch.int32, pin_memory=True)
+        out = self.lp.Outputs(g, self.dev, with_vertex_point=False, with_labels=False)
+        out.counts = d_block[0:6].view(torch.int64)
+        out.labels = d_block[8:8 + Vc]
+        out.vertex_point = d_block[8 + Vc:8 + 2 * Vc]
         bs = dict(
             xyz=torch.empty((g.n_rings * g.n_azimuth, 3), dtype=torch.float32, device=self.dev),
-            out=self.lp.Outputs(g, self.dev),
-            h_labels=torch.empty(max(V, 1), dtype=torch.int32, pin_memory=True),
-            h_vpoint=torch.empty(max(V, 1), dtype=torch.int32, pin_memory=True),
-            h_counts=torch.empty(3, dtype=torch.int64, pin_memory=True),
+            out=out, d_block=d_block, h_block=h_block, h_np=h_block.numpy(), Vc=Vc,
         )
         if self.copy_mesh:
             bs["h_normals"] = torch.empty((max(V, 1), 3), dtype=torch.float32, pin_memory=True)
@@ -291,9 +298,7 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             for bs in sets:
                 o = bs["out"]
-                bs["h_counts"].copy_(o.counts, non_blocking=True)
-                bs["h_labels"].copy_(o.labels, non_blocking=True)
-                bs["h_vpoint"].copy_(o.vertex_point, non_blocking=True)
+                bs["h_block"].copy_(bs["d_block"], non_blocking=True)
                 if self.copy_mesh:
                     bs["h_normals"].copy_(o.normals, non_blocking=True)
                     bs["h_vertices"].copy_(o.vertices, non_blocking=True)
@@ -308,9 +313,9 @@ class GpuExecutor:
     def results(self, h):
         out = []
         for r, bs in zip(h["reqs"], h["sets"]):
-            V, T, K = bs["h_counts"].tolist()
-            res = dict(counts=(V, T, K), labels=bs["h_labels"][:V].numpy().copy(),
-                       vertex_point=bs["h_vpoint"][:V].numpy().copy())
+            h, Vc = bs["h_np"], bs["Vc"]
+            V, T, K = (int(x) for x in h[0:6].view(np.int64))
+            res = dict(counts=(V, T, K), labels=h[8:8 + V].copy(), vertex_point=h[8 + Vc:8 + Vc + V].copy())
             if self.copy_mesh:
                 res["normals"] = bs["h_normals"][:V].numpy().copy()
                 res["vertices"] = bs["h_vertices"][:V].numpy().copy()
