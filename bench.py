@@ -169,6 +169,52 @@ def accuracy_run(args, lp, synth, torch, ctx, frames, geos, stream):
             "batch": batch, "paper_shape_32x1800": paper, "paper_shape_environments": n_env}
 
 
+# The paper's own per-sweep times (Table 1: its C++ implementation on a
+# 7th-generation Intel Core i5 with 8 GB DDR4; 32 rings x 1800 firings; mesh,
+# normals and segmentation), quoted beside ours as context only.
+PAPER_MS_PER_SWEEP = {5: 54.33, 10: 35.06, 15: 25.53}
+
+
+def paper_shape_timing(lp, synth, torch, ctx, stream, reps=50):
+    """The paper's sweep shape (32 x 1800, street scenes) at sampling intervals
+    5, 10 and 15, inputs resident in HBM: one sweep per call (plain chain and
+    graph replay, back to back: GPU time per sweep) and 64 sweeps per batched
+    call (points/s)."""
+    dev = torch.device("cuda", 0)
+    params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2))
+    envs = synth.workload_frames("paper_32x1800", 8)
+    res = {}
+
+    def timed(prep, launch, n):
+        for _ in range(3):
+            ctx.lidar_mesh_segment(prep, stream, launch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            ctx.lidar_mesh_segment(prep, stream, launch)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e3
+
+    for s in (5, 10, 15):
+        geos = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, s, 1, f.sensor.az0) for f in envs]
+        xs = [torch.from_numpy(f.xyz).to(dev) for f in envs]
+        one_out = [lp.Outputs(geos[0], dev)]
+        one = ctx.prepare([(xs[0], geos[0], None)], params, one_out)
+        row = {"paper_ms_per_sweep": PAPER_MS_PER_SWEEP[s]}
+        for launch in ("plain", "graph"):
+            row[f"{launch}_ms_per_sweep"] = round(timed(one, launch, reps), 4)
+        items = [(xs[k % 8], geos[k % 8], None) for k in range(64)]
+        outs = [lp.Outputs(g, dev) for _, g, _ in items]
+        batch = ctx.prepare(items, params, outs)
+        ms = timed(batch, "batched", reps)
+        row["batched64_points_per_s"] = round(sum(int(x.shape[0]) for x, _, _ in items) / (ms * 1e-3), 1)
+        res[str(s)] = row
+        log(f"  paper shape, interval {s}: {row}")
+    return {"workload": "32 rings x 1800 firings, street scenes (8 environments), inputs resident in HBM",
+            "paper_hardware": "C++ on a 7th-generation Intel Core i5, 8 GB DDR4 (Table 1; context only)",
+            "intervals": res}
+
+
 def rocm_version():
     """The ROCm release the library was built against, as installed."""
     try:
@@ -212,7 +258,8 @@ def main():
                     help="also time the batched form with this many batches in flight (1 = skip)")
     ap.add_argument("--forms", default="graph,batched,plain",
                     help="launch forms to time (graph is always timed: it gives value)")
-    ap.add_argument("--no-accuracy", action="store_true", help="skip the edge-score leg")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the edge-score leg and the timing at the paper's sweep shape")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (3 times), as the yardstick "
                          "for HBM byte counters")
@@ -367,10 +414,12 @@ def main():
     alg_path = 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T   # whole path, as in the byte model
     path_gbs = alg_path / (ms_best * 1e-3) / 1e9
 
-    accuracy = None
+    accuracy = paper_timing = None
     if not args.no_accuracy:
         log("edge scores")
         accuracy = accuracy_run(args, lp, synth, torch, ctx, frames, geos, stream)
+        log("the paper's sweep shape")
+        paper_timing = paper_shape_timing(lp, synth, torch, ctx, stream)
 
     served = None
     if args.served_seconds > 0:
@@ -440,6 +489,7 @@ def main():
         "roofline": roofline,
         "served": served,
         "accuracy": accuracy,
+        "paper_shape_timing": paper_timing,
         "cpu_baseline": cpu,
     }
     ctx.close()
