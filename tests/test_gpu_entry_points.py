@@ -113,7 +113,7 @@ def test_mesh_normals_refuse_label_outputs(ctx):
         ctx.lidar_mesh_segment(prep)
 
 
-@pytest.mark.parametrize("launch", ["plain", "graph"])
+@pytest.mark.parametrize("launch", ["plain", "batched", "graph"])
 def test_label_grid_on_oracle_normals(ctx, launch):
     import torch
     import paper_2005_02704_amd as lp
