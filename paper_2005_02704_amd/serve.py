@@ -288,10 +288,10 @@ class GpuExecutor:
         inputs, outs = [], []
         with torch.cuda.stream(stream):
             for r, bs in zip(reqs, sets):
-                n = r.n_points
-                if n:
-                    bs["xyz"][:n].copy_(r.xyz, non_blocking=True)
-                inputs.append((bs["xyz"][:n], self.geos[r.sensor], None))
+                dst = bs["xyz"][:r.n_points]
+                if r.n_points:
+                    dst.copy_(r.xyz, non_blocking=True)
+                inputs.append((dst, self.geos[r.sensor], None))
                 outs.append(bs["out"])
         prep = self.ctxs[slot].prepare(inputs, self.params, outs)
         self.ctxs[slot].lidar_mesh_segment(prep, stream=stream, launch=self.launch)
