@@ -17,7 +17,11 @@
  *     last failure is available from lidar_ctx_last_error().  Argument errors are
  *     reported before anything is enqueued.
  *   - A context is used by one host thread at a time; contexts are independent and
- *     may run concurrently on different streams.
+ *     may run concurrently on different streams.  The calls made on one context
+ *     are ordered on the device even when they name different streams: they share
+ *     the context's workspace, so a call on another stream than the context's
+ *     previous call first makes its stream wait (hipStreamWaitEvent) for the end
+ *     of that call.  Work of other streams and contexts is not waited for.
  *
  * Lattice conventions (see also the readings in the repository's design notes)
  *   - Ring i = 0 is the topmost laser, counting downwards; elevations are given
@@ -75,10 +79,13 @@ typedef struct {
     const lidar_sensor_t* sensor;  /* host */
     const float* xyz;              /* device, [n_points][3] FP32, any order */
     int64_t n_points;              /* 0 .. 2^31-1 */
-    const float* normals_in;       /* device [V][3] or NULL.  When given, the normal
+    const float* normals_in;       /* device [>= V][3] or NULL.  When given, the normal
                                       stage is skipped and these per-vertex normals
                                       (zero vector = no normal) are labelled instead;
-                                      V must be this frame's vertex count. */
+                                      row v is vertex v's normal, and the buffer must
+                                      hold at least this frame's vertex count V of
+                                      rows (max_vertices of lidar_query_sizes always
+                                      suffices; the kernels read rows 0 .. V-1). */
     const int32_t* truth_ids;      /* device [n_points] or NULL: ground-truth surface id
                                       of every input point, read only for the edge
                                       scores (lidar_result_t.edge_counts) */

@@ -54,6 +54,7 @@ struct lidar_ctx {
     hipEvent_t done[2] = {nullptr, nullptr};  // end of the call that last used h_table[b]
     bool pending[2] = {false, false};
     int flip = 0;
+    hipStream_t last_stream = nullptr;  // stream of the previous call (its end is done[flip ^ 1])
 
     // captured batched chain
     // Two instantiations of the same captured chain, launched alternately, so a
@@ -512,8 +513,8 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
                 return c->fail(LIDAR_ENOMEM, "cannot allocate the key grid");
             }
             // every chain resets the cells it used, so this fill happens once
-            e = hipMemsetAsync(c->keys, 0xFF, sizeof(uint64_t) * cap, stream);
-            if (e != hipSuccess) return c->hip_fail(e, "hipMemsetAsync");
+            e = fill_keys_empty(c->keys, cap, stream);
+            if (e != hipSuccess) return c->hip_fail(e, "key grid fill");
             c->keys_cap = cap;
         }
         if (tiles > c->tiles_cap) {
@@ -597,6 +598,15 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
             }
             c->table_cap = cap;
         }
+    }
+
+    // ---- calls on one context are ordered ----
+    // Every call reuses the context's workspace and device table, so a call on
+    // another stream than the previous one first waits, on the device, for
+    // that call's end.  (Growth above already waited for it on the host.)
+    if (c->pending[c->flip ^ 1] && stream != c->last_stream) {
+        e = hipStreamWaitEvent(stream, c->done[c->flip ^ 1], 0);
+        if (e != hipSuccess) return c->hip_fail(e, "hipStreamWaitEvent");
     }
 
     // ---- fill a pinned table (after the call that used it last has finished) ----
@@ -783,6 +793,7 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
     e = hipEventRecord(c->done[buf], stream);
     if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
     c->pending[buf] = true;
+    c->last_stream = stream;
     c->flip ^= 1;
     c->err.clear();
     return LIDAR_OK;

@@ -113,6 +113,10 @@ struct LaunchCfg {
 // Tile shapes (cells per tile, threads per tile workgroup) the kernels are built for.
 bool tile_shape_supported(int tile_cells, int tile_threads);
 
+// Sets n keys to KEY_EMPTY with a fill kernel (not a memset node, so the fill
+// also behaves when a caller captures it into a graph).
+hipError_t fill_keys_empty(uint64_t* keys, int64_t n, hipStream_t stream);
+
 // Enqueues the chain; when stage_events is non-null (N_STAGES + 1 events) an
 // event is recorded before the first kernel and after each kernel.
 hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const LaunchCfg& cfg,

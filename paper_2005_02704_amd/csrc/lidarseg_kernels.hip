@@ -1525,6 +1525,19 @@ void launch_tile_stages(const BatchHeader* d_hdr, const Workspace& ws, int g_cou
 
 }  // namespace
 
+namespace {
+__global__ __launch_bounds__(256) void k_fill_keys(uint64_t* __restrict__ keys, int64_t n) {
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) keys[c] = KEY_EMPTY;
+}
+}  // namespace
+
+hipError_t fill_keys_empty(uint64_t* keys, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    k_fill_keys<<<(int)(blocks < 4096 ? blocks : 4096), 256, 0, stream>>>(keys, n);
+    return hipGetLastError();
+}
+
 bool tile_shape_supported(int tile_cells, int tile_threads) {
     return (tile_threads == 256 && (tile_cells == 512 || tile_cells == 1024 || tile_cells == 2048)) ||
            (tile_threads == 512 && (tile_cells == 1024 || tile_cells == 2048));

@@ -197,6 +197,53 @@ class Outputs:
                     else None)
 
 
+def check_tensor(name, t, device, dtype, min_rows, cols=None, optional=False):
+    """Refuse (LidarError, LIDAR_EINVAL) a tensor the library could not read or
+    write safely: not on `device`, not contiguous, of another dtype, with fewer
+    than min_rows rows, or (cols given) not [rows, cols].  Nothing is launched."""
+    if t is None:
+        if optional:
+            return
+        raise LidarError(LIDAR_EINVAL, f"{name} is required")
+    if t.device != device:
+        raise LidarError(LIDAR_EINVAL, f"{name} is on {t.device}, not {device}")
+    if t.dtype != dtype:
+        raise LidarError(LIDAR_EINVAL, f"{name} is {t.dtype}, not {dtype}")
+    if not t.is_contiguous():
+        raise LidarError(LIDAR_EINVAL, f"{name} is not contiguous")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise LidarError(LIDAR_EINVAL, f"{name} has shape {tuple(t.shape)}, not [rows, {cols}]")
+    if cols is None and t.dim() != 1:
+        raise LidarError(LIDAR_EINVAL, f"{name} has shape {tuple(t.shape)}, not [rows]")
+    rows = t.shape[0]
+    if rows < min_rows:
+        raise LidarError(LIDAR_EINVAL, f"{name} has {rows} rows, needs at least {min_rows}")
+
+
+def check_frame(device, xyz, sensor, normals_in, truth, rings, out, n_points=None):
+    """Every tensor of one frame against what the library reads and writes:
+    xyz float32 [N, 3]; normals_in float32 [>= max_vertices, 3]; truth ids int32
+    [N]; reported rings uint8 [N]; outputs at the capacities lidar_query_sizes
+    gives (vertices and normals float32 [V, 3], labels and vertex_point int32 [V],
+    triangles int32 [T, 3], counts int64 [3], point_labels int32 [N], edge counts
+    int64 [4]).  V, T = max_vertices, max_triangles of the sensor."""
+    import torch
+    check_tensor("xyz", xyz, device, torch.float32, 0, 3)
+    N = int(xyz.shape[0])
+    V, T = lidar_query_sizes(sensor)
+    check_tensor("normals_in", normals_in, device, torch.float32, V, 3, optional=True)
+    check_tensor("truth_ids", truth, device, torch.int32, N, optional=True)
+    check_tensor("ring_ids", rings, device, torch.uint8, N, optional=True)
+    check_tensor("vertices", out.vertices, device, torch.float32, V, 3)
+    check_tensor("normals", out.normals, device, torch.float32, V, 3)
+    check_tensor("labels", out.labels, device, torch.int32, V, optional=True)
+    check_tensor("triangles", out.triangles, device, torch.int32, T, 3)
+    check_tensor("vertex_point", out.vertex_point, device, torch.int32, V, optional=True)
+    check_tensor("counts", out.counts, device, torch.int64, 3)
+    check_tensor("point_labels", out.point_labels, device, torch.int32, N, optional=True)
+    check_tensor("edge_counts", out.edge_counts, device, torch.int64, 4, optional=True)
+
+
 class LidarContext:
     """A lidar_ctx: device workspace and captured graph, used by one thread at a time."""
 
@@ -245,7 +292,11 @@ class LidarContext:
 
     def prepare(self, inputs, params: lidar_params_t, outputs):
         """Build the C argument arrays once (for repeated launches on the same buffers)."""
+        import torch
         n = len(inputs)
+        if len(outputs) != n:
+            raise LidarError(LIDAR_EINVAL, f"{n} inputs but {len(outputs)} outputs")
+        dev = torch.device("cuda", self.device)
         frames = (lidar_frame_t * n)()
         results = (lidar_result_t * n)()
         keep = []
@@ -253,6 +304,10 @@ class LidarContext:
             xyz, sensor, normals_in = item[:3]
             truth = item[3] if len(item) > 3 else None
             rings = item[4] if len(item) > 4 else None
+            try:
+                check_frame(dev, xyz, sensor, normals_in, truth, rings, outputs[f])
+            except LidarError as err:
+                raise LidarError(err.code, f"frame {f}: {err}") from None
             sc = sensor.c_struct()
             keep.append(sc)
             frames[f] = lidar_frame_t(ctypes.pointer(sc), xyz.data_ptr() if xyz.numel() else None,

@@ -60,13 +60,17 @@ class Server:
       bytes_for(req) -> int         device bytes a request needs while in flight
       submit(slot, reqs) -> handle  enqueue the group; returns at once
       poll(handle) -> bool          True once the group's outputs are on the host
-      results(handle) -> list       per-request result dicts (after poll is True)
+      results(handle) -> list       per-request result dicts (after poll is True);
+                                    the group's buffers go back to their pools
+      discard(handle)               (after poll is True) the group's buffers go back
+                                    to their pools without reading its results
 
     timeout_s: a watchdog on each group.  A group still running that long after
     submission fails its requests (failed = "timeout"; they are finished and
     counted, without results), so callers are never left waiting.  Its slot and
     memory stay held until the device work really completes (the work may
-    still write into them), and are then released silently.
+    still write into them), and are then released silently: the executor
+    discards the group, returning its buffers to their pools.
     """
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 64, timeout_s: float | None = None):
@@ -130,6 +134,8 @@ class Server:
                         r.t_done = now
                         r.result = res
                         self.done.append(r)
+                else:
+                    self.ex.discard(st.handle)
                 self.in_use -= st.bytes_held
                 st.busy, st.batch, st.handle, st.bytes_held, st.abandoned = False, [], None, 0, False
             elif (self.timeout_s is not None and not st.abandoned
@@ -323,6 +329,10 @@ class GpuExecutor:
             out.append(res)
             self.free_sets[r.sensor].append(bs)
         return out
+
+    def discard(self, h):
+        for r, bs in zip(h["reqs"], h["sets"]):
+            self.free_sets[r.sensor].append(bs)
 
     def close(self):
         self.torch.cuda.synchronize()

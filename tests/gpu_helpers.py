@@ -15,6 +15,16 @@ def geometry(sensor, s=1, wrap=1):
     return lp.SensorGeometry(sensor.elevations(), sensor.n_azimuth, s, wrap, sensor.az0)
 
 
+def pad_normals(normals, sensor, s=1):
+    """Caller-given normals (one row per vertex) padded with zero rows to the
+    sensor's vertex capacity H * W / s, the size the binding asks for."""
+    n = np.ascontiguousarray(normals, np.float32).reshape(-1, 3)
+    rows = sensor.n_rings * (sensor.n_azimuth // s)
+    out = np.zeros((max(rows, n.shape[0]), 3), np.float32)
+    out[:n.shape[0]] = n
+    return out
+
+
 def run_gpu(ctx, items, launch="plain", r_min=1.0, r_max=60.0, thr=THR, predicate=0, cos_min=0.0, min_segment=0,
             point_labels=False, score_radius=None):
     """items: list of (xyz float32 [N,3] numpy, synth.Sensor, s, wrap, normals_in or None
@@ -26,7 +36,7 @@ def run_gpu(ctx, items, launch="plain", r_min=1.0, r_max=60.0, thr=THR, predicat
     for it in items:
         xyz, sen, s, wrap, nin = it[:5]
         x = torch.from_numpy(np.ascontiguousarray(xyz, np.float32)).cuda()
-        n = torch.from_numpy(np.ascontiguousarray(nin, np.float32)).cuda() if nin is not None else None
+        n = torch.from_numpy(pad_normals(nin, sen, s)).cuda() if nin is not None else None
         tr = torch.from_numpy(np.ascontiguousarray(it[5], np.int32)).cuda() if len(it) > 5 and it[5] is not None \
             else None
         rg = torch.from_numpy(np.ascontiguousarray(it[6], np.uint8)).cuda() if len(it) > 6 else None

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import check_geometry, geometry, run_gpu, run_oracle
+from gpu_helpers import check_geometry, geometry, pad_normals, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -97,7 +97,7 @@ def test_mesh_normals_refuse_label_outputs(ctx):
     geo = geometry(f.sensor)
     x = torch.from_numpy(f.xyz).cuda()
     dev = torch.device("cuda", 0)
-    nin = torch.zeros((f.n_points, 3), dtype=torch.float32, device=dev)
+    nin = torch.zeros((geo.n_rings * geo.n_cols, 3), dtype=torch.float32, device=dev)
     truth = torch.zeros(f.n_points, dtype=torch.int32, device=dev)
     cases = [([(x, geo, nin)], [lp.Outputs(geo, dev)]),
              ([(x, geo, None)], [lp.Outputs(geo, dev, n_points=f.n_points)]),
@@ -123,7 +123,7 @@ def test_label_grid_on_oracle_normals(ctx, launch):
     inputs, outs = [], []
     for (xyz, sen, s, wrap), r in zip(items, refs):
         geo = geometry(sen, s, wrap)
-        inputs.append((torch.from_numpy(xyz).cuda(), geo, torch.from_numpy(r.normals).cuda()))
+        inputs.append((torch.from_numpy(xyz).cuda(), geo, torch.from_numpy(pad_normals(r.normals, sen, s)).cuda()))
         outs.append(lp.Outputs(geo, dev))
     prep = ctx.prepare(inputs, lp.make_params(), outs)
     ctx.lidar_label_grid(prep, launch=launch)
@@ -201,3 +201,97 @@ def test_stage_times(ctx):
         assert full[k][0] > 0, k
     for k in ("bin", "geom", "flatten"):
         assert mesh[k][0] > 0, k
+
+
+def test_calls_on_one_context_alternate_streams(ctx):
+    """Calls on one context name different streams without any host wait in
+    between: each call first waits (on the device) for the context's previous
+    call, since they share its workspace, so every output equals the same call
+    made alone; the geometry also matches the oracle."""
+    import torch
+    import paper_2005_02704_amd as lp
+    dev = torch.device("cuda", 0)
+    frames_a = synth.batch_frames(24, 31)
+    frames_b = [synth.workload_frames("c4_128x4096")[0], synth.workload_frames("c1_16x1800")[0]]
+    s_b = (2, 1)
+
+    def prep(frames, subs):
+        geos = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, s, 1, f.sensor.az0)
+                for f, s in zip(frames, subs)]
+        outs = [lp.Outputs(g, dev) for g in geos]
+        return ctx.prepare([(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)],
+                           lp.make_params(), outs), outs
+
+    def snap(outs):
+        return [(o.counts.cpu().clone(), o.labels.cpu().clone(), o.normals.cpu().clone(),
+                 o.triangles.cpu().clone()) for o in outs]
+
+    def same(a, b):
+        for (ca, la, na, ta), (cb, lb, nb, tb) in zip(a, b):
+            V, T = int(ca[0]), int(ca[1])
+            if not (torch.equal(ca, cb) and torch.equal(la[:V], lb[:V]) and torch.equal(na[:V], nb[:V])
+                    and torch.equal(ta[:T], tb[:T])):
+                return False
+        return True
+
+    pa, oa = prep(frames_a, [1] * len(frames_a))
+    pb, ob = prep(frames_b, s_b)
+    pa2, oa2 = prep(frames_a, [1] * len(frames_a))
+    pb2, ob2 = prep(frames_b, s_b)
+    # alone, one call at a time
+    for launch in ("batched", "graph"):
+        ctx.lidar_mesh_segment(pa, launch=launch)
+        torch.cuda.synchronize()
+        ref_a = snap(oa)
+        ctx.lidar_mesh_segment(pb, launch=launch)
+        torch.cuda.synchronize()
+        ref_b = snap(ob)
+        for rep in range(3):
+            for o in oa + ob + oa2 + ob2:
+                o.labels.fill_(-7)
+                o.counts.fill_(-7)
+            torch.cuda.synchronize()
+            sa, sb = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+            ctx.lidar_mesh_segment(pa, stream=sa, launch=launch)
+            ctx.lidar_mesh_segment(pb, stream=sb, launch=launch)
+            ctx.lidar_mesh_segment(pa2, stream=sa, launch=launch)
+            ctx.lidar_mesh_segment(pb2, stream=sb, launch=launch)
+            torch.cuda.synchronize()
+            assert same(snap(oa), ref_a) and same(snap(oa2), ref_a), (launch, rep)
+            assert same(snap(ob), ref_b) and same(snap(ob2), ref_b), (launch, rep)
+    for f, s, o in zip(frames_b, s_b, ob2):
+        t = o.trimmed()
+        g = dict(vertices=t["vertices"].cpu().numpy(), normals=t["normals"].cpu().numpy(),
+                 triangles=t["triangles"].cpu().numpy(), vertex_point=t["vertex_point"].cpu().numpy(),
+                 counts=t["counts"])
+        check_geometry(g, run_oracle(f.xyz, f.sensor, s))
+
+
+def test_prepare_refuses_unsafe_tensors(ctx):
+    """The binding refuses, before any launch, tensors the kernels would read or
+    write out of bounds: host memory, another dtype, a transposed view, normals
+    or outputs smaller than the sensor's capacities."""
+    import torch
+    import paper_2005_02704_amd as lp
+    dev = torch.device("cuda", 0)
+    f = synth.workload_frames("c1_16x1800")[0]
+    geo = geometry(f.sensor)
+    V, T = lp.lidar_query_sizes(geo)
+    x = torch.from_numpy(f.xyz).to(dev)
+    good = lp.Outputs(geo, dev)
+    short = lp.Outputs(geo, dev)
+    short.normals = short.normals[:V // 2]
+    bad_inputs = [
+        ([(torch.from_numpy(f.xyz), geo, None)], [good]),                       # host tensor
+        ([(x.double(), geo, None)], [good]),                                    # float64
+        ([(x.t().contiguous().t(), geo, None)], [good]),                        # transposed view
+        ([(x, geo, torch.zeros((V - 1, 3), device=dev))], [good]),              # short normals_in
+        ([(x, geo, None)], [short]),                                            # short output
+    ]
+    for inputs, outs in bad_inputs:
+        with pytest.raises(lp.LidarError) as e:
+            ctx.prepare(inputs, lp.make_params(), outs)
+        assert e.value.code == lp.LIDAR_EINVAL
+    # the context still works
+    g = run_gpu(ctx, [(f.xyz, f.sensor, 1, 1, None)])[0]
+    check_geometry(g, run_oracle(f.xyz, f.sensor))

@@ -78,8 +78,8 @@ def test_scores_in_every_launch_form(ctx):
     # a batch where only some frames ask for scores, and then none: the others are untouched
     import torch
     import paper_2005_02704_amd as lp
-    from gpu_helpers import geometry
-    inputs = [(torch.from_numpy(f.xyz).cuda(), geometry(f.sensor), torch.from_numpy(r.normals).cuda(),
+    from gpu_helpers import geometry, pad_normals
+    inputs = [(torch.from_numpy(f.xyz).cuda(), geometry(f.sensor), torch.from_numpy(pad_normals(r.normals, f.sensor)).cuda(),
                torch.from_numpy(f.prim.astype(np.int32)).cuda()) for f, r in zip(frames, refs)]
     outs = [lp.Outputs(geometry(f.sensor), torch.device("cuda", 0), scores=(k % 2 == 0)) for k, f in enumerate(frames)]
     prep = ctx.prepare(inputs, lp.make_params(score_radius=2), outs)

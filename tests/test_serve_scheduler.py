@@ -11,31 +11,47 @@ from paper_2005_02704_amd.serve import Request, Server, poisson_schedule
 
 
 class FakeExecutor:
-    """Completes a group `delay` seconds after submission; results from the oracle."""
+    """Completes a group `delay` seconds after submission; results from the oracle.
+    Each request holds one buffer set of its sensor's pool while in flight, as the
+    GPU executor's resident sets are held."""
 
-    def __init__(self, n_slots, delay, sensors):
+    def __init__(self, n_slots, delay, sensors, sets_per_sensor=2):
         self.n_slots = n_slots
         self.delay = delay
         self.sensors = sensors
         self.submitted = []
+        self.free_sets = [[object() for _ in range(sets_per_sensor)] for _ in sensors]
+        self.sets_made = sets_per_sensor * len(sensors)
 
     def bytes_for(self, req):
         return 12 * req.n_points
 
+    def _buffer_set(self, sensor):
+        if self.free_sets[sensor]:
+            return self.free_sets[sensor].pop()
+        self.sets_made += 1
+        return object()
+
     def submit(self, slot, reqs):
         self.submitted.append((slot, [r.rid for r in reqs]))
-        return dict(t_ready=time.perf_counter() + self.delay, reqs=reqs)
+        return dict(t_ready=time.perf_counter() + self.delay, reqs=reqs,
+                    sets=[self._buffer_set(r.sensor) for r in reqs])
 
     def poll(self, h):
         return time.perf_counter() >= h["t_ready"]
 
     def results(self, h):
         out = []
-        for r in h["reqs"]:
+        for r, bs in zip(h["reqs"], h["sets"]):
             sen = self.sensors[r.sensor]
             res = oracle.mesh_segment(r.xyz, sen.n_rings, sen.n_azimuth, 1, sen.elevations())
             out.append(dict(labels=res.labels, counts=res.counts))
+            self.free_sets[r.sensor].append(bs)
         return out
+
+    def discard(self, h):
+        for r, bs in zip(h["reqs"], h["sets"]):
+            self.free_sets[r.sensor].append(bs)
 
 
 @pytest.fixture(scope="module")
@@ -154,7 +170,18 @@ def test_watchdog_fails_a_stuck_group_and_keeps_its_slot(frames):
     assert all(done[k].slot != stuck_slot for k in range(1, 6))
     # its memory is released only when the device work completes
     assert srv.in_use == ex.bytes_for(done[0])
+    assert sum(len(p) for p in ex.free_sets) == ex.sets_made - 1   # the stuck group holds one set
     ex.release = True
     srv.step()
     assert srv.in_use == 0 and not any(st.busy for st in srv.slots)
     assert len(srv.done) == 6   # the late completion adds no second result
+    # the abandoned group's buffer set went back to its pool: every set made is free again
+    assert sum(len(p) for p in ex.free_sets) == ex.sets_made
+    # so later requests of that sensor reuse the pool instead of making new sets
+    made = ex.sets_made
+    for rid in range(6, 10):
+        srv.submit(make(rid, 0, rid % 3, time.perf_counter()))
+    while not srv.idle():
+        srv.step()
+        time.sleep(1e-3)
+    assert ex.sets_made == made
