@@ -309,7 +309,9 @@ class LidarContext:
             except LidarError as err:
                 raise LidarError(err.code, f"frame {f}: {err}") from None
             sc = sensor.c_struct()
-            keep.append(sc)
+            # the struct points into the geometry's own elevation array, so the
+            # prepared call holds the geometry as well as the struct
+            keep.append((sensor, sc))
             frames[f] = lidar_frame_t(ctypes.pointer(sc), xyz.data_ptr() if xyz.numel() else None,
                                       int(xyz.shape[0]),
                                       normals_in.data_ptr() if normals_in is not None else None,
@@ -319,14 +321,28 @@ class LidarContext:
             # the prepared call holds the tensors whose pointers it carries, so
             # none of them is freed (and its memory reused) while the call lives
             keep.append((xyz, normals_in, truth, rings, outputs[f]))
-        return (frames, n, params, results, keep)
+        return (frames, n, params, results, keep, set())
 
     def _call(self, fn, prepared, stream, launch):
         import torch
-        frames, n, params, results, _keep = prepared
+        frames, n, params, results, keep, recorded = prepared
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         mode = LAUNCH[launch] if isinstance(launch, str) else int(launch)
+        if stream.cuda_stream not in recorded:
+            # torch's caching allocator reuses a freed tensor's memory once the
+            # stream it was allocated on has passed the free; a call on another
+            # stream is made known to it, so no buffer of the call is handed out
+            # again while the call may still read or write it (once per stream:
+            # the allocator waits on every recorded stream when the tensor is freed)
+            for item in keep:
+                if isinstance(item, tuple) and len(item) == 5:
+                    xyz, normals_in, truth, rings, out = item
+                    for t in (xyz, normals_in, truth, rings, out.vertices, out.normals, out.labels,
+                              out.triangles, out.vertex_point, out.counts, out.point_labels, out.edge_counts):
+                        if t is not None and t.numel():
+                            t.record_stream(stream)
+            recorded.add(stream.cuda_stream)
         self._check(fn(self._h, frames, n, ctypes.byref(params), results, ctypes.c_void_p(stream.cuda_stream), mode))
 
     def lidar_mesh_segment(self, prepared, stream=None, launch: str | int = "batched"):
