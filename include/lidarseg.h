@@ -190,6 +190,34 @@ int lidar_label_grid(lidar_ctx* ctx, const lidar_frame_t* frames, int32_t n_fram
                      const lidar_params_t* params, lidar_result_t* results,
                      void* stream, int32_t launch);
 
+/* For callers that cannot allocate memory -- code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation: lidar_mesh_segment
+ * (same arguments, same kernels, same outputs bit for bit) that calls no
+ * hipMalloc, hipFree, hipHostMalloc or other allocating routine.  Differences:
+ *   - the workspace and the descriptor table live in one fixed array of
+ *     LIDAR_NOALLOC_SCRATCH_BYTES of device memory per GPU, which the GPU holds
+ *     from the library's first use on it until the process ends (the pinned host
+ *     staging of the table is made by lidar_ctx_create).  A call that needs more
+ *     (roughly 12 bytes per lattice cell of the batch, 12 more per cell when
+ *     point labels, segment removal or edge scores are asked for, 4 per input
+ *     point with point labels) returns LIDAR_ENOMEM before anything is
+ *     enqueued; the message gives the bytes needed;
+ *   - launch is LIDAR_LAUNCH_PLAIN or LIDAR_LAUNCH_BATCHED (LIDAR_EINVAL for
+ *     LIDAR_LAUNCH_GRAPH, which would create a graph), and n_frames is at most
+ *     LIDAR_NOALLOC_MAX_FRAMES;
+ *   - every call on one GPU uses that GPU's one array, which keeps the last
+ *     call's contents (each call first resets the state the kernels expect).
+ *     Calls made on one context are ordered as for every entry point; calls of
+ *     different contexts on one GPU that overlap on the device race, so the
+ *     caller orders them (one stream, or events);
+ *   - per-stage timing (lidar_ctx_set_profiling) does not record these calls,
+ *     and the context's own workspace (lidar_ctx_workspace_bytes) is not used. */
+#define LIDAR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define LIDAR_NOALLOC_MAX_FRAMES 64
+int lidar_mesh_segment_noalloc(lidar_ctx* ctx, const lidar_frame_t* frames, int32_t n_frames,
+                               const lidar_params_t* params, lidar_result_t* results,
+                               void* stream, int32_t launch);
+
 /* Device workspace.  A context grows its workspace when a call needs more
  * (by half as much again as asked for, to reallocate rarely) and keeps it until
  * it is destroyed.  With a limit set (max_bytes > 0; 0 = none), a call whose

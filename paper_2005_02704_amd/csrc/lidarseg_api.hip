@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,7 +21,54 @@ namespace {
 
 thread_local std::string g_last_error;
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Pinned staging of the descriptor table of lidar_mesh_segment_noalloc: the
+// larger of the batched table and the plain tables of LIDAR_NOALLOC_MAX_FRAMES
+// frames of LIDAR_MAX_RINGS rings each.
+constexpr size_t NOALLOC_TABLE_BATCHED =
+    align_up(sizeof(BatchHeader) + sizeof(FrameDesc) * LIDAR_NOALLOC_MAX_FRAMES, 8) +
+    8 * (size_t)LIDAR_NOALLOC_MAX_FRAMES * LIDAR_MAX_RINGS;
+constexpr size_t NOALLOC_TABLE_PLAIN =
+    LIDAR_NOALLOC_MAX_FRAMES * align_up(sizeof(BatchHeader) + sizeof(FrameDesc) + 8 * (size_t)LIDAR_MAX_RINGS, 256);
+constexpr size_t NOALLOC_TABLE_BYTES =
+    NOALLOC_TABLE_BATCHED > NOALLOC_TABLE_PLAIN ? NOALLOC_TABLE_BATCHED : NOALLOC_TABLE_PLAIN;
+
+// The workspace of lidar_mesh_segment_noalloc: one fixed array per GPU, which
+// each GPU holds from the library's first use on it until the process ends.
+// On the host this name only stands for the symbol: host code never passes it
+// to a kernel or a copy, but the device address looked up for each device.
+static __device__ __align__(256) unsigned char scratch[LIDAR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_looked_up[SCRATCH_MAX_DEVICES] = {};
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+hipError_t g_scratch_err[SCRATCH_MAX_DEVICES] = {};
+
+// Looks up the device address of `scratch` on `device`, which must be the
+// current device, once per device (every GPU holds its own copy of the array at
+// its own address).
+void scratch_lookup(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_looked_up[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();  // the failure is reported by the entry point
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_looked_up[device] = true;
+}
+
+// The device address of `scratch` on `device` (looked up by lidar_ctx_create),
+// or nullptr with the lookup's error.
+void* scratch_address(int device, hipError_t* err) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) { *err = hipErrorInvalidDevice; return nullptr; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *err = g_scratch_looked_up[device] ? g_scratch_err[device] : hipErrorNotInitialized;
+    return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -50,6 +98,8 @@ struct lidar_ctx {
     int64_t aux_cells_cap = 0;    // capacity of cvid, segsize and vtruth
     char* d_table = nullptr;      // descriptor tables + elevations
     char* h_table[2] = {nullptr, nullptr};  // pinned staging of d_table, used alternately
+    char* na_table[2] = {nullptr, nullptr}; // pinned staging of lidar_mesh_segment_noalloc's table
+                                            // (NOALLOC_TABLE_BYTES each, made with the context)
     size_t table_cap = 0;
     hipEvent_t done[2] = {nullptr, nullptr};  // end of the call that last used h_table[b]
     bool pending[2] = {false, false};
@@ -228,7 +278,16 @@ int lidar_ctx_create(int device, lidar_ctx** out) {
     for (int b = 0; b < 2; ++b) {
         e = hipEventCreateWithFlags(&c->done[b], hipEventDisableTiming);
         if (e != hipSuccess) { g_last_error = hipGetErrorString(e); lidar_ctx_destroy(c); return LIDAR_EDEVICE; }
+        e = hipHostMalloc(&c->na_table[b], NOALLOC_TABLE_BYTES, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            c->na_table[b] = nullptr;
+            g_last_error = "cannot allocate the pinned table staging";
+            lidar_ctx_destroy(c);
+            return LIDAR_ENOMEM;
+        }
     }
+    // the no-allocation entry point's scratch address on this device (once per device)
+    scratch_lookup(device);
     *out = c;
     return LIDAR_OK;
 }
@@ -256,6 +315,7 @@ void lidar_ctx_destroy(lidar_ctx* c) {
     if (c->d_table) (void)hipFree(c->d_table);
     for (int b = 0; b < 2; ++b) {
         if (c->h_table[b]) (void)hipHostFree(c->h_table[b]);
+        if (c->na_table[b]) (void)hipHostFree(c->na_table[b]);
         if (c->done[b]) (void)hipEventDestroy(c->done[b]);
     }
     delete c;
@@ -348,13 +408,21 @@ struct CallRange {
     ~CallRange() { roctxRangePop(); }
 };
 
-int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const lidar_params_t* params,
-              lidar_result_t* results, void* stream_, int32_t launch, CallMode mode) {
-    if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
-    const CallRange range(mode == CALL_MESH_ONLY ? "lidar_mesh_normals"
-                          : mode == CALL_LABEL_GRID ? "lidar_label_grid" : "lidar_mesh_segment");
+// What one call needs: sums over its frames (batched and graph forms), or the
+// largest frame (plain form: the frames run one after another on shared
+// workspace offsets).
+struct CallTotals {
+    int64_t cells = 0, border_slots = 0, elev_total = 0, tiles = 0, pblk = 0, vitems = 0;
+    int64_t labelled_points = 0;  // point records (frames asking for point labels)
+    bool any_point_labels = false, any_score = false, prune = false, post = false, aux = false;
+    size_t table_bytes = 0;       // descriptor table (header, descriptors, elevations)
+};
+
+// Host-side validation of every argument and the plan of each frame; nothing
+// is enqueued.  plan has n_frames entries.
+int plan_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const lidar_params_t* params,
+              const lidar_result_t* results, int32_t launch, CallMode mode, FramePlan* plan, CallTotals& tot) {
     const bool mesh_only = mode == CALL_MESH_ONLY;
-    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     if (n_frames < 1 || !frames || !results) return c->fail(LIDAR_EINVAL, "need n_frames >= 1 frames and results");
     if (!params) return c->fail(LIDAR_EINVAL, "params is NULL");
     if (launch != LIDAR_LAUNCH_PLAIN && launch != LIDAR_LAUNCH_BATCHED && launch != LIDAR_LAUNCH_GRAPH)
@@ -374,12 +442,8 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
         if (params->min_segment < 0) return c->fail(LIDAR_EINVAL, "min_segment must be >= 0");
     }
 
-    // ---- plan ----
-    std::vector<FramePlan> plan(n_frames);
-    int64_t cells = 0, border_slots = 0, elev_total = 0;
-    int64_t tiles = 0, pblk = 0, vitems = 0, labelled_points = 0, max_points_f = 0;
-    bool any_point_labels = false, any_score = false;
-    int64_t max_cells = 0, max_tiles_f = 0, max_pblk_f = 0, max_vitem_f = 0, max_border_f = 0;
+    tot = CallTotals();
+    int64_t max_points_f = 0, max_cells = 0, max_tiles_f = 0, max_vitem_f = 0, max_border_f = 0;
     for (int f = 0; f < n_frames; ++f) {
         const lidar_frame_t& fr = frames[f];
         std::string msg;
@@ -397,8 +461,8 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
             if ((int64_t)fr.sensor->n_rings * fr.sensor->n_azimuth > INT32_MAX)
                 return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) +
                                                  ": point labels need n_rings * n_azimuth below 2^31");
-            any_point_labels = true;
-            labelled_points += fr.n_points;
+            tot.any_point_labels = true;
+            tot.labelled_points += fr.n_points;
             max_points_f = std::max<int64_t>(max_points_f, fr.n_points);
         }
         if (fr.n_points > 0 && !fr.xyz)
@@ -408,7 +472,7 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
                 return c->fail(LIDAR_EINVAL, "frame " + std::to_string(f) + ": edge scores need truth_ids");
             if (params->score_radius < 0 || params->score_radius > LIDAR_MAX_SCORE_RADIUS)
                 return c->fail(LIDAR_EINVAL, "score_radius must lie in [0, LIDAR_MAX_SCORE_RADIUS]");
-            any_score = true;
+            tot.any_score = true;
         }
         const lidar_result_t& r = results[f];
         if (!r.vertices || !r.normals || (!r.labels && !mesh_only) || !r.triangles || !r.counts)
@@ -425,55 +489,213 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
         p.cells = (int64_t)p.H * p.Wp;
         p.n_vitem = (int)((p.cells + VITEM - 1) / VITEM);
         p.border_slots = (int64_t)p.n_tiles * 2 * p.H;
-        cells += p.cells;
-        border_slots += p.border_slots;
-        elev_total += p.H;
-        tiles += p.n_tiles;
-        pblk += p.n_pblk;
-        vitems += p.n_vitem;
+        tot.cells += p.cells;
+        tot.border_slots += p.border_slots;
+        tot.elev_total += p.H;
+        tot.tiles += p.n_tiles;
+        tot.pblk += p.n_pblk;
+        tot.vitems += p.n_vitem;
         max_cells = std::max(max_cells, p.cells);
         max_tiles_f = std::max<int64_t>(max_tiles_f, p.n_tiles);
-        max_pblk_f = std::max<int64_t>(max_pblk_f, p.n_pblk);
         max_vitem_f = std::max<int64_t>(max_vitem_f, p.n_vitem);
         max_border_f = std::max(max_border_f, p.border_slots);
     }
-    if (tiles > INT32_MAX || pblk > INT32_MAX || cells > MAX_BATCH_CELLS || border_slots > INT32_MAX)
+    if (tot.tiles > INT32_MAX || tot.pblk > INT32_MAX || tot.cells > MAX_BATCH_CELLS ||
+        tot.border_slots > INT32_MAX)
         return c->fail(LIDAR_EINVAL, "batch too large (at most 2^31 - 1024 lattice cells in one call)");
-    const bool prune = !mesh_only && params->min_segment > 1;
-    const bool post = prune || any_point_labels;
-    // plain launches run the frames one after another on shared workspace offsets
-    if (launch == LIDAR_LAUNCH_PLAIN) {
-        labelled_points = max_points_f;
-        cells = max_cells;
-        tiles = max_tiles_f;
-        vitems = max_vitem_f;
-        border_slots = max_border_f;
-    }
-
-    hipError_t e = hipSetDevice(c->device);
-    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
-
+    tot.prune = !mesh_only && params->min_segment > 1;
+    tot.post = tot.prune || tot.any_point_labels;
+    tot.aux = tot.any_point_labels || tot.prune || tot.any_score;
     // table bytes: batched = one header, all descs, elevations; plain = one
     // (header, desc, elevations) group per frame.
-    const size_t desc_bytes = sizeof(FrameDesc);
-    size_t table_bytes;
     if (launch == LIDAR_LAUNCH_PLAIN) {
-        table_bytes = 0;
         for (int f = 0; f < n_frames; ++f)
-            table_bytes += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
+            tot.table_bytes += align_up(sizeof(BatchHeader) + sizeof(FrameDesc) + 8 * (size_t)plan[f].H, 256);
+        // plain launches run the frames one after another on shared workspace offsets
+        tot.labelled_points = max_points_f;
+        tot.cells = max_cells;
+        tot.tiles = max_tiles_f;
+        tot.vitems = max_vitem_f;
+        tot.border_slots = max_border_f;
     } else {
-        table_bytes = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) + 8 * (size_t)elev_total;
+        tot.table_bytes = align_up(sizeof(BatchHeader) + sizeof(FrameDesc) * n_frames, 8) + 8 * (size_t)tot.elev_total;
     }
+    return LIDAR_OK;
+}
 
-    // ---- capacity ----
+// Makes `stream` wait (on the device) for the context's previous call when
+// that call was enqueued on another stream: calls on one context share its
+// workspace and device table.
+int order_after_previous_call(lidar_ctx* c, hipStream_t stream) {
+    if (c->pending[c->flip ^ 1] && stream != c->last_stream) {
+        const hipError_t e = hipStreamWaitEvent(stream, c->done[c->flip ^ 1], 0);
+        if (e != hipSuccess) return c->hip_fail(e, "hipStreamWaitEvent");
+    }
+    return LIDAR_OK;
+}
+
+// Fills the descriptor table in the pinned host buffer htab (header,
+// descriptors and elevations; for plain launches one group per frame at
+// group_off[f]), copies it to d_table on `stream` and enqueues the kernels:
+// one chain per frame (plain) or one chain over the batch (batched).  The
+// graph form is launched by the caller from the same table.
+int enqueue_table_and_chains(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
+                             const lidar_params_t* params, const lidar_result_t* results, const FramePlan* plan,
+                             const CallTotals& tot, int32_t launch, bool mesh_only, hipStream_t stream,
+                             const Workspace& ws, char* d_table, char* htab, bool profile) {
+    const size_t desc_bytes = sizeof(FrameDesc);
+    std::memset(htab, 0, tot.table_bytes);
+    const double rmin = params->r_min, rmax = params->r_max;
+    auto fill_desc = [&](FrameDesc& d, int f, int64_t cell_off, int64_t border_off, int64_t pt_off, int tile_off,
+                         int pblk_off, int vitem_off, int elev_off) {
+        const lidar_frame_t& fr = frames[f];
+        const lidar_result_t& r = results[f];
+        const FramePlan& p = plan[f];
+        d.xyz = fr.xyz;
+        d.normals_in = fr.normals_in;
+        d.vertices = r.vertices;
+        d.normals = r.normals;
+        d.labels = r.labels;
+        d.tris = r.triangles;
+        d.vpoint = r.vertex_point;
+        d.counts = r.counts;
+        d.n_points = fr.n_points;
+        d.cell_off = cell_off;
+        d.border_off = border_off;
+        d.pt_off = pt_off;
+        d.point_labels = r.point_labels;
+        d.truth = r.edge_counts ? fr.truth_ids : nullptr;
+        d.rings = fr.ring_ids;
+        d.scores = r.edge_counts;
+        d.score_r = params->score_radius;
+        d.pred = params->predicate;
+        d.min_seg = mesh_only ? 0 : params->min_segment;
+        d.cos_min = params->cos_min;
+        d.H = p.H; d.W = p.W; d.s = p.s; d.Wp = p.Wp; d.wrap = p.wrap; d.TW = p.TW;
+        d.n_tiles = p.n_tiles; d.tile_off = tile_off;
+        d.n_pblk = p.n_pblk; d.pblk_off = pblk_off;
+        d.n_vitem = p.n_vitem; d.vitem_off = vitem_off;
+        d.elev_off = elev_off;
+        d.az0 = fr.sensor->az0_rad;
+        d.dphi = 2.0 * M_PI / (double)p.W;
+        d.rmin2 = rmin * rmin;
+        d.rmax2 = rmax * rmax;
+        d.thr[0] = params->thr[0]; d.thr[1] = params->thr[1]; d.thr[2] = params->thr[2];
+        std::memcpy(htab + 8 * (size_t)elev_off, fr.sensor->elev_rad, 8 * (size_t)p.H);
+    };
+    hipError_t e;
+    if (launch == LIDAR_LAUNCH_PLAIN) {
+        size_t off = 0;
+        for (int f = 0; f < n_frames; ++f) {
+            BatchHeader* h = reinterpret_cast<BatchHeader*>(htab + off);
+            h->n_frames = 1;
+            h->total_tiles = plan[f].n_tiles;
+            h->total_pblk = plan[f].n_pblk;
+            h->total_vitems = plan[f].n_vitem;
+            h->total_border = (int)plan[f].border_slots;
+            h->post = (tot.prune || results[f].point_labels) ? 1 : 0;
+            const size_t elev_byte = off + sizeof(BatchHeader) + desc_bytes;
+            // frames run one after another on the stream, so they share workspace offsets
+            fill_desc(*h->frames(), f, 0, 0, 0, 0, 0, 0, (int)(elev_byte / 8));
+            off += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
+        }
+        e = hipMemcpyAsync(d_table, htab, tot.table_bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync");
+        off = 0;
+        for (int f = 0; f < n_frames; ++f) {
+            LaunchCfg cfg;
+            cfg.tile_cells = c->tile_cells;
+            cfg.tile_threads = c->tile_threads;
+            cfg.max_tiles = plan[f].n_tiles;
+            cfg.max_pblk = plan[f].n_pblk;
+            cfg.max_vitems = plan[f].n_vitem;
+            cfg.max_border = (int)plan[f].border_slots;
+            cfg.max_frames = 1;
+            cfg.post = tot.prune || results[f].point_labels;
+            cfg.score = results[f].edge_counts != nullptr;
+            cfg.mesh_only = mesh_only;
+            cfg.grid = std::max(std::max(plan[f].n_tiles, plan[f].n_pblk), plan[f].n_vitem);
+            hipEvent_t* ev = profile ? c->new_event_set() : nullptr;
+            e = launch_chain(reinterpret_cast<const BatchHeader*>(d_table + off), ws, cfg, stream, ev);
+            if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
+            off += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
+        }
+        return LIDAR_OK;
+    }
+    BatchHeader* h = reinterpret_cast<BatchHeader*>(htab);
+    h->n_frames = n_frames;
+    h->total_tiles = (int)tot.tiles;
+    h->total_pblk = (int)tot.pblk;
+    h->total_vitems = (int)tot.vitems;
+    h->total_border = (int)tot.border_slots;
+    h->post = tot.post ? 1 : 0;
+    FrameDesc* d = h->frames();
+    const size_t elev_base = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) / 8;
+    int64_t cell_off = 0, border_off = 0, pt_off = 0;
+    int tile_off = 0, pblk_off = 0, vitem_off = 0, elev_off = (int)elev_base;
+    for (int f = 0; f < n_frames; ++f) {
+        fill_desc(d[f], f, cell_off, border_off, pt_off, tile_off, pblk_off, vitem_off, elev_off);
+        cell_off += plan[f].cells;
+        border_off += plan[f].border_slots;
+        if (results[f].point_labels) pt_off += frames[f].n_points;
+        tile_off += plan[f].n_tiles;
+        pblk_off += plan[f].n_pblk;
+        vitem_off += plan[f].n_vitem;
+        elev_off += plan[f].H;
+    }
+    // the device table is read only by this call's kernels, which run after
+    // this copy in stream order; the next call's copy follows them likewise
+    e = hipMemcpyAsync(d_table, htab, tot.table_bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync");
+    if (launch == LIDAR_LAUNCH_BATCHED) {
+        LaunchCfg cfg;
+        cfg.tile_cells = c->tile_cells;
+        cfg.tile_threads = c->tile_threads;
+        cfg.max_tiles = (int)tot.tiles;
+        cfg.max_pblk = (int)tot.pblk;
+        cfg.max_vitems = (int)tot.vitems;
+        cfg.max_border = (int)tot.border_slots;
+        cfg.max_frames = n_frames;
+        cfg.post = tot.post;
+        cfg.score = tot.any_score;
+        cfg.mesh_only = mesh_only;
+        cfg.grid = c->grid_wg > 0 ? c->grid_wg : 4 * c->cu_count;
+        std::copy(c->stage_grid, c->stage_grid + N_STAGES, cfg.stage_grid);
+        hipEvent_t* ev = profile ? c->new_event_set() : nullptr;
+        e = launch_chain(reinterpret_cast<const BatchHeader*>(d_table), ws, cfg, stream, ev);
+        if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
+    }
+    return LIDAR_OK;
+}
+
+// Records the end of the call that used pinned table `buf` on `stream`.
+int finish_call(lidar_ctx* c, int buf, hipStream_t stream) {
+    const hipError_t e = hipEventRecord(c->done[buf], stream);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+    c->pending[buf] = true;
+    c->last_stream = stream;
+    c->flip ^= 1;
+    c->err.clear();
+    return LIDAR_OK;
+}
+
+// Grows the context's workspace (and descriptor-table staging) to hold a call
+// with these totals; the graph is dropped when anything is reallocated.
+// Growth waits for the context's earlier calls and for the device.
+int ensure_capacity(lidar_ctx* c, const CallTotals& tot, hipStream_t stream) {
+    const int64_t cells = tot.cells, tiles = tot.tiles, vitems = tot.vitems, border_slots = tot.border_slots;
+    const int64_t labelled_points = tot.labelled_points;
+    const bool any_point_labels = tot.any_point_labels;
+    const size_t table_bytes = tot.table_bytes;
+    hipError_t e;
+    const bool aux_needed = tot.aux;
     const bool grow = cells > c->keys_cap || tiles > c->tiles_cap || vitems > c->vitems_cap ||
                       border_slots > c->border_cap || table_bytes > c->table_cap ||
                       (any_point_labels && labelled_points > c->pcell_cap) ||
-                      ((any_point_labels || prune || any_score) && cells > c->aux_cells_cap);
+                      (aux_needed && cells > c->aux_cells_cap);
     // new capacities: half as much again as asked for, so that a slowly
     // growing stream of batches reallocates rarely, unless that slack would
     // break the context's workspace limit
-    const bool aux_needed = any_point_labels || prune || any_score;
     int64_t n_keys = c->keys_cap, n_tiles = c->tiles_cap, n_vitems = c->vitems_cap, n_pcell = c->pcell_cap,
             n_aux = c->aux_cells_cap, n_border = c->border_cap;
     size_t n_table = c->table_cap;
@@ -600,13 +822,45 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
         }
     }
 
+    return LIDAR_OK;
+}
+
+int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const lidar_params_t* params,
+              lidar_result_t* results, void* stream_, int32_t launch, CallMode mode) {
+    if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
+    const CallRange range(mode == CALL_MESH_ONLY ? "lidar_mesh_normals"
+                          : mode == CALL_LABEL_GRID ? "lidar_label_grid" : "lidar_mesh_segment");
+    const bool mesh_only = mode == CALL_MESH_ONLY;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+
+    // ---- plan ----
+    std::vector<FramePlan> plan(n_frames > 0 ? n_frames : 0);
+    CallTotals tot;
+    {
+        const int rc = plan_call(c, frames, n_frames, params, results, launch, mode, plan.data(), tot);
+        if (rc) return rc;
+    }
+    const int64_t cells = tot.cells, tiles = tot.tiles, vitems = tot.vitems, border_slots = tot.border_slots;
+    const int64_t labelled_points = tot.labelled_points;
+    const bool any_point_labels = tot.any_point_labels, any_score = tot.any_score, post = tot.post;
+    const size_t table_bytes = tot.table_bytes;
+
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+
+    // ---- capacity ----
+    {
+        const int rc = ensure_capacity(c, tot, stream);
+        if (rc) return rc;
+    }
+
     // ---- calls on one context are ordered ----
     // Every call reuses the context's workspace and device table, so a call on
     // another stream than the previous one first waits, on the device, for
     // that call's end.  (Growth above already waited for it on the host.)
-    if (c->pending[c->flip ^ 1] && stream != c->last_stream) {
-        e = hipStreamWaitEvent(stream, c->done[c->flip ^ 1], 0);
-        if (e != hipSuccess) return c->hip_fail(e, "hipStreamWaitEvent");
+    {
+        const int rc = order_after_previous_call(c, stream);
+        if (rc) return rc;
     }
 
     // ---- fill a pinned table (after the call that used it last has finished) ----
@@ -615,188 +869,154 @@ int mesh_call(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const
         int rc = c->wait_buffer(buf);
         if (rc) return rc;
     }
-    char* const htab = c->h_table[buf];
-    std::memset(htab, 0, table_bytes);
-    auto fill_desc = [&](FrameDesc& d, int f, int64_t cell_off, int64_t border_off, int64_t pt_off, int tile_off,
-                         int pblk_off, int vitem_off, int elev_off) {
-        const lidar_frame_t& fr = frames[f];
-        const lidar_result_t& r = results[f];
-        const FramePlan& p = plan[f];
-        d.xyz = fr.xyz;
-        d.normals_in = fr.normals_in;
-        d.vertices = r.vertices;
-        d.normals = r.normals;
-        d.labels = r.labels;
-        d.tris = r.triangles;
-        d.vpoint = r.vertex_point;
-        d.counts = r.counts;
-        d.n_points = fr.n_points;
-        d.cell_off = cell_off;
-        d.border_off = border_off;
-        d.pt_off = pt_off;
-        d.point_labels = r.point_labels;
-        d.truth = r.edge_counts ? fr.truth_ids : nullptr;
-        d.rings = fr.ring_ids;
-        d.scores = r.edge_counts;
-        d.score_r = params->score_radius;
-        d.pred = params->predicate;
-        d.min_seg = mesh_only ? 0 : params->min_segment;
-        d.cos_min = params->cos_min;
-        d.H = p.H; d.W = p.W; d.s = p.s; d.Wp = p.Wp; d.wrap = p.wrap; d.TW = p.TW;
-        d.n_tiles = p.n_tiles; d.tile_off = tile_off;
-        d.n_pblk = p.n_pblk; d.pblk_off = pblk_off;
-        d.n_vitem = p.n_vitem; d.vitem_off = vitem_off;
-        d.elev_off = elev_off;
-        d.az0 = fr.sensor->az0_rad;
-        d.dphi = 2.0 * M_PI / (double)p.W;
-        d.rmin2 = rmin * rmin;
-        d.rmax2 = rmax * rmax;
-        d.thr[0] = params->thr[0]; d.thr[1] = params->thr[1]; d.thr[2] = params->thr[2];
-        std::memcpy(htab + 8 * (size_t)elev_off, fr.sensor->elev_rad, 8 * (size_t)p.H);
-    };
-
-    Workspace ws = c->workspace();
-    const int auto_grid = c->grid_wg > 0 ? c->grid_wg : 4 * c->cu_count;
-
-    if (launch == LIDAR_LAUNCH_PLAIN) {
-        std::vector<size_t> offs(n_frames);
-        size_t off = 0;
-        for (int f = 0; f < n_frames; ++f) {
-            offs[f] = off;
-            BatchHeader* h = reinterpret_cast<BatchHeader*>(htab + off);
-            h->n_frames = 1;
-            h->total_tiles = plan[f].n_tiles;
-            h->total_pblk = plan[f].n_pblk;
-            h->total_vitems = plan[f].n_vitem;
-            h->total_border = (int)plan[f].border_slots;
-            h->post = (prune || results[f].point_labels) ? 1 : 0;
-            FrameDesc* d = h->frames();
-            const size_t elev_byte = off + sizeof(BatchHeader) + desc_bytes;
-            // frames run one after another on the stream, so they share workspace offsets
-            fill_desc(*d, f, 0, 0, 0, 0, 0, 0, (int)(elev_byte / 8));
-            off += align_up(sizeof(BatchHeader) + desc_bytes + 8 * (size_t)plan[f].H, 256);
-        }
-        e = hipMemcpyAsync(c->d_table, htab, table_bytes, hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync");
-        for (int f = 0; f < n_frames; ++f) {
+    const Workspace ws = c->workspace();
+    {
+        const int rc = enqueue_table_and_chains(c, frames, n_frames, params, results, plan.data(), tot, launch,
+                                                mesh_only, stream, ws, c->d_table, c->h_table[buf], c->profiling);
+        if (rc) return rc;
+    }
+    if (launch == LIDAR_LAUNCH_GRAPH) {
+        const int auto_grid = c->grid_wg > 0 ? c->grid_wg : 4 * c->cu_count;
+        // The captured chain uses fixed grid-stride grids and reads the batch
+        // from the device table, so it serves every batch that fits the workspace.
+        if (!c->graph_valid || c->graph_table_bytes != c->table_cap || c->graph_tile_cells != c->tile_cells ||
+            c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid || c->graph_post != post ||
+            c->graph_score != any_score || c->graph_mesh_only != mesh_only) {
+            // a replay of the old graph may still run: wait for this
+            // context's earlier calls before destroying it
+            int rc = c->wait_idle();
+            if (rc) return rc;
+            c->drop_graph();
+            hipStream_t cap_stream;
+            e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return c->hip_fail(e, "hipStreamCreate");
+            e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) { (void)hipStreamDestroy(cap_stream); return c->hip_fail(e, "hipStreamBeginCapture"); }
             LaunchCfg cfg;
             cfg.tile_cells = c->tile_cells;
             cfg.tile_threads = c->tile_threads;
-            cfg.max_tiles = plan[f].n_tiles;
-            cfg.max_pblk = plan[f].n_pblk;
-            cfg.max_vitems = plan[f].n_vitem;
-            cfg.max_border = (int)plan[f].border_slots;
-            cfg.max_frames = 1;
-            cfg.post = prune || results[f].point_labels;
-            cfg.score = results[f].edge_counts != nullptr;
-            cfg.mesh_only = mesh_only;
-            cfg.grid = std::max(std::max(plan[f].n_tiles, plan[f].n_pblk), plan[f].n_vitem);
-            hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
-            e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table + offs[f]), ws, cfg, stream, ev);
-            if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
-        }
-    } else {
-        BatchHeader* h = reinterpret_cast<BatchHeader*>(htab);
-        h->n_frames = n_frames;
-        h->total_tiles = (int)tiles;
-        h->total_pblk = (int)pblk;
-        h->total_vitems = (int)vitems;
-        h->total_border = (int)border_slots;
-        h->post = post ? 1 : 0;
-        FrameDesc* d = h->frames();
-        const size_t elev_base = align_up(sizeof(BatchHeader) + desc_bytes * n_frames, 8) / 8;
-        int64_t cell_off = 0, border_off = 0, pt_off = 0;
-        int tile_off = 0, pblk_off = 0, vitem_off = 0, elev_off = (int)elev_base;
-        for (int f = 0; f < n_frames; ++f) {
-            fill_desc(d[f], f, cell_off, border_off, pt_off, tile_off, pblk_off, vitem_off, elev_off);
-            cell_off += plan[f].cells;
-            border_off += plan[f].border_slots;
-            if (results[f].point_labels) pt_off += frames[f].n_points;
-            tile_off += plan[f].n_tiles;
-            pblk_off += plan[f].n_pblk;
-            vitem_off += plan[f].n_vitem;
-            elev_off += plan[f].H;
-        }
-        // the device table is read only by this call's kernels, which run after
-        // this copy in stream order; the next call's copy follows them likewise
-        e = hipMemcpyAsync(c->d_table, htab, table_bytes, hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync");
-        if (launch == LIDAR_LAUNCH_BATCHED) {
-            LaunchCfg cfg;
-            cfg.tile_cells = c->tile_cells;
-            cfg.tile_threads = c->tile_threads;
-            cfg.max_tiles = (int)tiles;
-            cfg.max_pblk = (int)pblk;
-            cfg.max_vitems = (int)vitems;
-            cfg.max_border = (int)border_slots;
-            cfg.max_frames = n_frames;
+            cfg.max_tiles = (int)std::min<int64_t>(c->tiles_cap, INT32_MAX);
+            cfg.max_pblk = INT32_MAX;
+            cfg.max_vitems = (int)std::min<int64_t>(c->vitems_cap, INT32_MAX);
+            cfg.max_border = (int)std::min<int64_t>(c->border_cap, INT32_MAX);
+            cfg.max_frames = INT32_MAX;
             cfg.post = post;
             cfg.score = any_score;
             cfg.mesh_only = mesh_only;
             cfg.grid = auto_grid;
             std::copy(c->stage_grid, c->stage_grid + N_STAGES, cfg.stage_grid);
-            hipEvent_t* ev = c->profiling ? c->new_event_set() : nullptr;
-            e = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, stream, ev);
-            if (e != hipSuccess) return c->hip_fail(e, "kernel launch");
-        } else {
-            // The captured chain uses fixed grid-stride grids and reads the batch
-            // from the device table, so it serves every batch that fits the workspace.
-            if (!c->graph_valid || c->graph_table_bytes != c->table_cap || c->graph_tile_cells != c->tile_cells ||
-                c->graph_tile_threads != c->tile_threads || c->graph_grid != auto_grid || c->graph_post != post ||
-                c->graph_score != any_score || c->graph_mesh_only != mesh_only) {
-                // a replay of the old graph may still run: wait for this
-                // context's earlier calls before destroying it
-                int rc = c->wait_idle();
-                if (rc) return rc;
-                c->drop_graph();
-                hipStream_t cap_stream;
-                e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
-                if (e != hipSuccess) return c->hip_fail(e, "hipStreamCreate");
-                e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-                if (e != hipSuccess) { (void)hipStreamDestroy(cap_stream); return c->hip_fail(e, "hipStreamBeginCapture"); }
-                LaunchCfg cfg;
-                cfg.tile_cells = c->tile_cells;
-                cfg.tile_threads = c->tile_threads;
-                cfg.max_tiles = (int)std::min<int64_t>(c->tiles_cap, INT32_MAX);
-                cfg.max_pblk = INT32_MAX;
-                cfg.max_vitems = (int)std::min<int64_t>(c->vitems_cap, INT32_MAX);
-                cfg.max_border = (int)std::min<int64_t>(c->border_cap, INT32_MAX);
-                cfg.max_frames = INT32_MAX;
-                cfg.post = post;
-                cfg.score = any_score;
-                cfg.mesh_only = mesh_only;
-                cfg.grid = auto_grid;
-                std::copy(c->stage_grid, c->stage_grid + N_STAGES, cfg.stage_grid);
-                hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
-                e = hipStreamEndCapture(cap_stream, &c->graph);
-                (void)hipStreamDestroy(cap_stream);
-                if (e2 != hipSuccess) return c->hip_fail(e2, "capture launch");
-                if (e != hipSuccess) return c->hip_fail(e, "hipStreamEndCapture");
-                for (auto& ge : c->graph_exec) {
-                    e = hipGraphInstantiate(&ge, c->graph, nullptr, nullptr, 0);
-                    if (e != hipSuccess) { c->drop_graph(); return c->hip_fail(e, "hipGraphInstantiate"); }
-                }
-                c->graph_valid = true;
-                c->graph_table_bytes = c->table_cap;
-                c->graph_tile_cells = c->tile_cells;
-                c->graph_tile_threads = c->tile_threads;
-                c->graph_grid = auto_grid;
-                c->graph_post = post;
-                c->graph_score = any_score;
-                c->graph_mesh_only = mesh_only;
+            hipError_t e2 = launch_chain(reinterpret_cast<const BatchHeader*>(c->d_table), ws, cfg, cap_stream);
+            e = hipStreamEndCapture(cap_stream, &c->graph);
+            (void)hipStreamDestroy(cap_stream);
+            if (e2 != hipSuccess) return c->hip_fail(e2, "capture launch");
+            if (e != hipSuccess) return c->hip_fail(e, "hipStreamEndCapture");
+            for (auto& ge : c->graph_exec) {
+                e = hipGraphInstantiate(&ge, c->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) { c->drop_graph(); return c->hip_fail(e, "hipGraphInstantiate"); }
             }
-            e = hipGraphLaunch(c->graph_exec[c->graph_next], stream);
-            c->graph_next ^= 1;
-            if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
+            c->graph_valid = true;
+            c->graph_table_bytes = c->table_cap;
+            c->graph_tile_cells = c->tile_cells;
+            c->graph_tile_threads = c->tile_threads;
+            c->graph_grid = auto_grid;
+            c->graph_post = post;
+            c->graph_score = any_score;
+            c->graph_mesh_only = mesh_only;
         }
+        e = hipGraphLaunch(c->graph_exec[c->graph_next], stream);
+        c->graph_next ^= 1;
+        if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
     }
-    e = hipEventRecord(c->done[buf], stream);
-    if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
-    c->pending[buf] = true;
-    c->last_stream = stream;
-    c->flip ^= 1;
-    c->err.clear();
-    return LIDAR_OK;
+    return finish_call(c, buf, stream);
+}
+
+// lidar_mesh_segment with the workspace and the device table carved out of the
+// per-device scratch array; allocates nothing.
+int mesh_call_noalloc(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames, const lidar_params_t* params,
+                      lidar_result_t* results, void* stream_, int32_t launch) {
+    if (!c) { g_last_error = "ctx is NULL"; return LIDAR_EINVAL; }
+    const CallRange range("lidar_mesh_segment_noalloc");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    if (launch == LIDAR_LAUNCH_GRAPH)
+        return c->fail(LIDAR_EINVAL, "lidar_mesh_segment_noalloc launches plain or batched chains only "
+                                     "(a graph would have to be created)");
+    if (n_frames > LIDAR_NOALLOC_MAX_FRAMES)
+        return c->fail(LIDAR_EINVAL, "lidar_mesh_segment_noalloc takes at most LIDAR_NOALLOC_MAX_FRAMES (" +
+                                         std::to_string(LIDAR_NOALLOC_MAX_FRAMES) + ") frames");
+    FramePlan plan[LIDAR_NOALLOC_MAX_FRAMES];
+    CallTotals tot;
+    {
+        const int rc = plan_call(c, frames, n_frames, params, results, launch, CALL_SEGMENT, plan, tot);
+        if (rc) return rc;
+    }
+    // the workspace's arrays, one after another at 256-byte boundaries
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = used;
+        used = align_up(used + bytes, 256);
+        return at;
+    };
+    const size_t o_keys = take(sizeof(uint64_t) * tot.cells);
+    const size_t o_forest = take(sizeof(int32_t) * tot.cells);
+    const size_t o_tiles = take(3 * sizeof(int32_t) * tot.tiles);
+    const size_t o_occ = take(OCC_WORDS * sizeof(uint64_t) * tot.tiles);
+    const size_t o_rootbits = take(VITEM_WORDS * sizeof(uint64_t) * tot.vitems);
+    const size_t o_wprefix = take(VITEM_WORDS * sizeof(uint32_t) * tot.vitems);
+    const size_t o_vroots = take(sizeof(int32_t) * tot.vitems);
+    const size_t o_border = take(sizeof(int2) * tot.border_slots);
+    const size_t o_pcell = take(tot.any_point_labels ? sizeof(int32_t) * tot.labelled_points : 0);
+    const size_t o_cvid = take(tot.aux ? sizeof(int32_t) * tot.cells : 0);
+    const size_t o_segsize = take(tot.aux ? sizeof(int32_t) * tot.cells : 0);
+    const size_t o_vtruth = take(tot.aux ? sizeof(int32_t) * tot.cells : 0);
+    const size_t o_table = take(tot.table_bytes);
+    if (used > LIDAR_NOALLOC_SCRATCH_BYTES)
+        return c->fail(LIDAR_ENOMEM, "the call needs " + std::to_string(used) +
+                                         " bytes of workspace, above the no-allocation scratch of " +
+                                         std::to_string((unsigned long long)LIDAR_NOALLOC_SCRATCH_BYTES) + " bytes");
+    if (tot.table_bytes > NOALLOC_TABLE_BYTES)  // cannot happen within the frame and ring limits
+        return c->fail(LIDAR_EINVAL, "descriptor table larger than its pinned staging");
+
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    char* const base = static_cast<char*>(scratch_address(c->device, &e));
+    if (!base) return c->hip_fail(e, "scratch address of this device");
+
+    {
+        const int rc = order_after_previous_call(c, stream);
+        if (rc) return rc;
+    }
+    const int buf = c->flip;
+    {
+        const int rc = c->wait_buffer(buf);
+        if (rc) return rc;
+    }
+    Workspace ws;
+    ws.keys = reinterpret_cast<uint64_t*>(base + o_keys);
+    ws.forest = reinterpret_cast<int32_t*>(base + o_forest);
+    ws.tile_v = reinterpret_cast<int32_t*>(base + o_tiles);
+    ws.tile_t = ws.tile_v + tot.tiles;
+    ws.tile_vbase = ws.tile_v + 2 * tot.tiles;
+    ws.occ = reinterpret_cast<uint64_t*>(base + o_occ);
+    ws.rootbits = reinterpret_cast<uint64_t*>(base + o_rootbits);
+    ws.wprefix = reinterpret_cast<uint32_t*>(base + o_wprefix);
+    ws.vitem_roots = reinterpret_cast<int32_t*>(base + o_vroots);
+    ws.border = reinterpret_cast<int2*>(base + o_border);
+    ws.pcell = tot.any_point_labels ? reinterpret_cast<int32_t*>(base + o_pcell) : nullptr;
+    ws.cvid = tot.aux ? reinterpret_cast<int32_t*>(base + o_cvid) : nullptr;
+    ws.segsize = tot.aux ? reinterpret_cast<int32_t*>(base + o_segsize) : nullptr;
+    ws.vtruth = tot.aux ? reinterpret_cast<int32_t*>(base + o_vtruth) : nullptr;
+    char* const d_table = base + o_table;
+    ws.elev = reinterpret_cast<const double*>(d_table);
+    // the array keeps whatever the last call on this GPU left in it: the key
+    // grid, the only state the chain expects, starts empty (a fill kernel)
+    e = fill_keys_empty(ws.keys, tot.cells, stream);
+    if (e != hipSuccess) return c->hip_fail(e, "key grid fill");
+    {
+        const int rc = enqueue_table_and_chains(c, frames, n_frames, params, results, plan, tot, launch, false,
+                                                stream, ws, d_table, c->na_table[buf], false);
+        if (rc) return rc;
+    }
+    return finish_call(c, buf, stream);
 }
 
 }  // namespace
@@ -816,6 +1036,12 @@ int lidar_mesh_normals(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_fram
 int lidar_label_grid(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
                      const lidar_params_t* params, lidar_result_t* results, void* stream, int32_t launch) {
     return mesh_call(c, frames, n_frames, params, results, stream, launch, CALL_LABEL_GRID);
+}
+
+int lidar_mesh_segment_noalloc(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,
+                               const lidar_params_t* params, lidar_result_t* results, void* stream,
+                               int32_t launch) {
+    return mesh_call_noalloc(c, frames, n_frames, params, results, stream, launch);
 }
 
 }  // extern "C"

@@ -33,10 +33,12 @@ EXPORTS = ("lidar_ctx_create", "lidar_ctx_destroy", "lidar_ctx_last_error", "lid
            "lidar_query_sizes", "lidar_mesh_segment", "lidar_mesh_normals", "lidar_label_grid",
            "lidar_ctx_set_workspace_limit", "lidar_ctx_workspace_bytes", "lidar_ctx_set_tuning",
            "lidar_ctx_set_stage_grid",
-           "lidar_ctx_set_profiling", "lidar_ctx_stage_times")
+           "lidar_ctx_set_profiling", "lidar_ctx_stage_times", "lidar_mesh_segment_noalloc")
 LIDAR_N_STAGES = 11
 STAGES = ("bin", "count", "geom", "cc", "merge", "compress", "flatten", "scan", "label", "post", "score")
 LIDAR_MAX_SCORE_RADIUS = 8
+LIDAR_NOALLOC_SCRATCH_BYTES = 64 << 20
+LIDAR_NOALLOC_MAX_FRAMES = 64
 
 
 class LidarError(RuntimeError):
@@ -98,7 +100,7 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(lidar_params_t), ctypes.POINTER(lidar_result_t),
                                      P, ctypes.c_int32]
     L.lidar_mesh_segment.restype = ctypes.c_int
-    for name in ("lidar_mesh_normals", "lidar_label_grid"):
+    for name in ("lidar_mesh_normals", "lidar_label_grid", "lidar_mesh_segment_noalloc"):
         getattr(L, name).argtypes = L.lidar_mesh_segment.argtypes
         getattr(L, name).restype = ctypes.c_int
     L.lidar_ctx_set_workspace_limit.argtypes = [P, ctypes.c_uint64]
@@ -356,6 +358,11 @@ class LidarContext:
     def lidar_label_grid(self, prepared, stream=None, launch: str | int = "batched"):
         """Enqueue lidar_label_grid (labels of caller-given normals)."""
         self._call(self._L.lidar_label_grid, prepared, stream, launch)
+
+    def lidar_mesh_segment_noalloc(self, prepared, stream=None, launch: str | int = "batched"):
+        """Enqueue lidar_mesh_segment_noalloc (plain or batched; workspace in the
+        GPU's fixed scratch array, nothing allocated by the library)."""
+        self._call(self._L.lidar_mesh_segment_noalloc, prepared, stream, launch)
 
     def set_workspace_limit(self, max_bytes: int):
         """Device workspace bytes this context may hold (0 = no limit)."""

@@ -84,3 +84,25 @@ def test_binding_refuses_to_run_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "refused" in r.stdout
+
+
+def test_binding_constants_match_the_header():
+    """Every #define of include/lidarseg.h that the binding restates has the
+    header's value (evaluated by the C compiler)."""
+    import subprocess
+    import tempfile
+    import paper_2005_02704_amd as lp
+    names = ["LIDAR_OK", "LIDAR_EINVAL", "LIDAR_ENOMEM", "LIDAR_EDEVICE", "LIDAR_MAX_RINGS", "LIDAR_LAUNCH_PLAIN",
+             "LIDAR_LAUNCH_BATCHED", "LIDAR_LAUNCH_GRAPH", "LIDAR_PRED_COMPONENTS", "LIDAR_PRED_COSINE",
+             "LIDAR_MAX_SCORE_RADIUS", "LIDAR_N_STAGES", "LIDAR_NOALLOC_SCRATCH_BYTES", "LIDAR_NOALLOC_MAX_FRAMES"]
+    body = "\n".join(f'printf("{n} %lld\\n", (long long)({n}));' for n in names)
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "consts.c")
+        exe = os.path.join(d, "consts")
+        open(src, "w").write("#include <stdio.h>\n#include \"lidarseg.h\"\nint main(void) {\n" + body +
+                             "\nreturn 0;\n}\n")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line)
+    for n in names:
+        assert int(got[n]) == getattr(lp, n), n
