@@ -17,9 +17,9 @@
 //   k_cc       per tile in LDS: similarity of joins, local segments           [Algorithm 1]
 //   k_merge    unions of the similar joins that cross tile borders             [Algorithm 1]
 //   k_compress pointer jumping on the segments joined across borders
-//   k_flatten  every vertex to its segment root; roots flagged; key cells reset
+//   k_flatten  segment roots flagged and counted; key cells reset
 //   k_scan     per frame: roots before each labelling item (their rank base)
-//   k_resolve  label = 1 + rank of the vertex's root; segment sizes
+//   k_resolve  every vertex's root; label = 1 + rank of that root; segment sizes
 //   k_post     (when asked for) segment removal and every input point's label  [Segmentation, last paragraph]
 //   k_score    (when asked for) edge scores of the labels against truth ids   [Section 3, evaluation]
 //
@@ -1164,11 +1164,11 @@ __global__ __launch_bounds__(NT) void k_compress(const BatchHeader* __restrict__
     }
 }
 
-// Roots.  Item b of a frame covers vertex slots [1024 b, 1024 b + 1024).  Every
-// vertex finds its segment root (a read-only walk) and leaves it, frame-local,
-// in its label slot for k_resolve; the roots of each 64-slot
-// word are flagged in rootbits, each word gets the item's roots before it, and
-// the item its root count.  The item's key cells are reset for the next call.
+// Roots.  Item b of a frame covers vertex slots [1024 b, 1024 b + 1024).  A
+// vertex is a segment root when its forest entry points at itself.  The roots
+// of each 64-slot word are flagged in rootbits, each word gets the item's roots
+// before it, and the item its root count.  The item's key cells are reset for
+// the next call.  (No walk is needed here: k_resolve finds each vertex's root.)
 template <int NT>
 __global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int RV = VITEM / NT;
@@ -1178,7 +1178,7 @@ __global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ 
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    int* const P = ws.forest;
+    const int* const P = ws.forest;
     for (int b = blockIdx.x; b < hdr->total_vitems; b += gridDim.x) {
         const FrameDesc* fd = F + frame_of<&FrameDesc::vitem_off>(F, nf, b);
         const int lb = b - fd->vitem_off;
@@ -1187,39 +1187,16 @@ __global__ __launch_bounds__(NT) void k_flatten(const BatchHeader* __restrict__ 
         const int v0 = lb * VITEM;
         const int64_t wbase = (int64_t)b * VITEM_WORDS;   // == vitem_off * 16 + lb * 16
         __syncthreads();  // s_w of the previous item has been read
-        // the item's walks advance together, one step per pass, so their loads overlap
-        int cur[RV];
-        uint32_t walking = 0;
+        int par[RV];
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int v = v0 + r * NT + threadIdx.x;
-            cur[r] = -1;
-            if (v < V) cur[r] = g_load(P + base + v);
+            par[r] = v < V ? P[base + v] : -1;
         }
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int v = v0 + r * NT + threadIdx.x;
-            if (v < V && cur[r] != base + v) walking |= 1u << r;
-        }
-        for (int it = 0; walking && it < WALK_LIMIT; ++it) {
-            int nxt[RV];
-#pragma unroll
-            for (int r = 0; r < RV; ++r) nxt[r] = ((walking >> r) & 1u) ? g_load(P + cur[r]) : cur[r];
-#pragma unroll
-            for (int r = 0; r < RV; ++r) {
-                if (((walking >> r) & 1u) && nxt[r] == cur[r]) walking &= ~(1u << r);
-                cur[r] = nxt[r];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RV; ++r) {
-            const int v = v0 + r * NT + threadIdx.x;
-            bool isroot = false;
-            if (v < V) {
-                gmem(fd->labels)[v] = cur[r] - base;
-                isroot = cur[r] == base + v;
-            }
-            const uint64_t bits = __ballot(isroot);
+            const uint64_t bits = __ballot(v < V && par[r] == base + v);
             if (lane == 0) {
                 ws.rootbits[wbase + r * NW + wv] = bits;
                 s_w[r * NW + wv] = __popcll(bits);
@@ -1303,27 +1280,53 @@ __global__ __launch_bounds__(NT) void k_scan(const BatchHeader* __restrict__ hdr
     }
 }
 
-// label = 1 + (roots of the frame before the vertex's root, which k_flatten
-// left in the vertex's label slot): the roots of the frame before the root's
-// item, of the item before its word, and of the word before it.
+// label = 1 + (roots of the frame before the vertex's root): the roots of the
+// frame before the root's item, of the item before its word, and of the word
+// before it.  The root is found by walking the forest: after k_compress every
+// vertex is at most two links from its root (its local root, then the root its
+// local root was joined to), and the walks of an item advance together, one
+// step per pass, so their loads overlap.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int RV = VITEM / NT;
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
+    const int* const P = ws.forest;
     for (int b = blockIdx.x; b < hdr->total_vitems; b += gridDim.x) {
         const FrameDesc* fd = F + frame_of<&FrameDesc::vitem_off>(F, nf, b);
         const int lb = b - fd->vitem_off;
         const int V = (int)max<int64_t>(fd->counts[0], 0);
+        const int base = (int)fd->cell_off;
         const int v0 = lb * VITEM;
         const int64_t wframe = (int64_t)fd->vitem_off * VITEM_WORDS;
         const int32_t* const ibase = ws.vitem_roots + fd->vitem_off;
+        int cur[RV];
+        uint32_t walking = 0;
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+            const int v = v0 + r * NT + threadIdx.x;
+            cur[r] = -1;
+            if (v < V) {
+                cur[r] = P[base + v];
+                if (cur[r] != base + v) walking |= 1u << r;
+            }
+        }
+        for (int it = 0; walking && it < WALK_LIMIT; ++it) {
+            int nxt[RV];
+#pragma unroll
+            for (int r = 0; r < RV; ++r) nxt[r] = ((walking >> r) & 1u) ? P[cur[r]] : cur[r];
+#pragma unroll
+            for (int r = 0; r < RV; ++r) {
+                if (((walking >> r) & 1u) && nxt[r] == cur[r]) walking &= ~(1u << r);
+                cur[r] = nxt[r];
+            }
+        }
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int v = v0 + r * NT + threadIdx.x;
             int lab = -1;
             if (v < V) {
-                const int root = gmem(fd->labels)[v];
+                const int root = cur[r] - base;
                 const int64_t w = wframe + (root >> 6);
                 const uint64_t below = ws.rootbits[w] & ((1ull << (root & 63)) - 1ull);
                 lab = 1 + ibase[root / VITEM] + (int)ws.wprefix[w] + __popcll(below);
