@@ -405,6 +405,9 @@ def lidar_mesh_segment(ctx: LidarContext, inputs, params: lidar_params_t | None 
     dev = torch.device("cuda", ctx.device)
     outs = [Outputs(item[1], dev, with_vertex_point, int(item[0].shape[0]) if point_labels else 0, scores)
             for item in inputs]
+    if stream is not None:
+        # the outputs were made (counts zero-filled) on the current stream
+        stream.wait_stream(torch.cuda.current_stream(dev))
     prep = ctx.prepare(inputs, params, outs)
     ctx.lidar_mesh_segment(prep, stream=stream, launch=launch)
     return outs

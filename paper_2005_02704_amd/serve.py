@@ -246,6 +246,9 @@ class GpuExecutor:
         for q in range(len(geometries)):
             for _ in range(sets_per_sensor):
                 self.free_sets[q].append(self._new_set(q))
+        # the sets made up front are filled on the current stream: finished
+        # before any slot stream uses them
+        torch.cuda.current_stream(self.dev).synchronize()
 
     def bytes_for(self, req) -> int:
         V, T = self.caps[req.sensor]
@@ -290,9 +293,11 @@ class GpuExecutor:
     def submit(self, slot, reqs):
         torch = self.torch
         stream = self.streams[slot]
-        sets = [self._buffer_set(r.sensor) for r in reqs]
         inputs, outs = [], []
         with torch.cuda.stream(stream):
+            # a set made here (its sensor's pool ran dry) is zero-filled on this
+            # slot's stream, so the fill is ordered before the group's kernels
+            sets = [self._buffer_set(r.sensor) for r in reqs]
             for r, bs in zip(reqs, sets):
                 dst = bs["xyz"][:r.n_points]
                 if r.n_points:
