@@ -68,10 +68,16 @@ def stage_bytes(stage, N, V, T):
 
 def served_run(args, lp, synth, torch):
     """8 simulated sensors (rings 16/32/64/128, widths 1024/2048/4096, 10-20 Hz
-    Poisson arrivals) through the continuous-batching server; then the same pool
-    with every request arriving at once (capacity), served in groups and, for
-    comparison, one sweep per call with plain per-frame launches."""
-    from paper_2005_02704_amd.serve import GpuExecutor, Request, Server, poisson_schedule
+    Poisson arrivals) through the native continuous-batching server, driven by
+    its native replay (no Python between arrival and completion); then the
+    same sensors at a hundred times their rates for 3 s (groups form under load); then the
+    pool with every request arriving at once (capacity), and for comparison the
+    same burst served one sweep per call with plain per-frame launches.
+    Latency runs from submission to the results in pinned host memory; every
+    rate includes the points' host-to-device copies and the results' copies back."""
+    import numpy as np
+    from paper_2005_02704_amd.lidarserve import LIDAR_SERVED_OK, NativeServer
+    from paper_2005_02704_amd.serve import poisson_schedule
     sensors = synth.served_sensors(8)
     n_pool = 3
     log(f"served: generating {8 * n_pool} pool sweeps")
@@ -79,47 +85,58 @@ def served_run(args, lp, synth, torch):
              for k in range(n_pool)] for q, (s, _) in enumerate(sensors)]
     geos = [lp.SensorGeometry(s.elevations(), s.n_azimuth, 1, 1, s.az0) for s, _ in sensors]
     pinned = [[torch.from_numpy(f.xyz).pin_memory() for f in row] for row in pool]
-
-    def make(rid, s, k, t):
-        return Request(rid, s, pinned[s][k], pool[s][k].n_points, t)
-
     budget = 1 << 30
-    ex = GpuExecutor(geos, n_slots=3, launch=args.served_launch)
-    # warm the slots (workspace growth, graph capture) before timing
-    warm = Server(ex, budget_bytes=budget, max_batch=16)
-    warm.run_schedule([(0.0, q, 0) for q in range(8)] * 3, make)
-    srv = Server(ex, budget_bytes=budget, max_batch=16, timeout_s=1.0)
-    sched = poisson_schedule([r for _, r in sensors], args.served_seconds, seed=args.seed, n_payloads=n_pool)
-    log(f"served: {len(sched)} sweeps over {args.served_seconds:.0f}s")
-    wall = srv.run_schedule(sched, make)
-    st = srv.stats(wall)
-    log(f"  p50 {st['p50_ms']:.2f} ms  p99 {st['p99_ms']:.2f} ms  {st['points_per_s']:.3e} points/s")
+
+    def replay(srv, sched):
+        lat, st, gs, wall = srv.replay([t for t, _, _ in sched], [q for _, q, _ in sched],
+                                       [pinned[q][k] for _, q, k in sched])
+        ok = st == LIDAR_SERVED_OK
+        pts = sum(int(pinned[q][k].shape[0]) for (_, q, k), good in zip(sched, ok) if good)
+        lat_ms = lat[ok] * 1e3
+        return {"requests": int(ok.sum()), "failed": int((~ok).sum()), "points": pts,
+                "points_per_s": round(pts / wall, 1),
+                "p50_ms": round(float(np.percentile(lat_ms, 50)), 4) if ok.any() else None,
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 4) if ok.any() else None,
+                "max_ms": round(float(lat_ms.max()), 4) if ok.any() else None,
+                "mean_batch": round(float(gs[ok].mean()), 3) if ok.any() else None,
+                "wall_s": round(wall, 3)}
+
+    rates = [r for _, r in sensors]
+    srv = NativeServer(geos, n_slots=3, max_batch=64, launch=args.served_launch, sets_per_sensor=24,
+                       budget_bytes=budget, timeout_s=1.0)
     burst = [(0.0, q % 8, (q // 8) % n_pool) for q in range(8 * 64)]
-    # one untimed burst first: the buffer sets the larger groups need (device
-    # outputs, pinned host copies) are allocated once, as a long-running server's are
-    Server(ex, budget_bytes=budget, max_batch=64).run_schedule(burst, make)
-    cap = Server(ex, budget_bytes=budget, max_batch=64)
-    wall_c = cap.run_schedule(burst, make)
-    stc = cap.stats(wall_c)
-    log(f"  capacity: {stc['points_per_s']:.3e} points/s ({stc['requests']} sweeps at once)")
-    ex.close()
-    # the same burst served one sweep per call with plain per-frame launches
-    ex_p = GpuExecutor(geos, n_slots=3, launch="plain")
-    Server(ex_p, budget_bytes=budget, max_batch=1).run_schedule(burst, make)
-    cap_p = Server(ex_p, budget_bytes=budget, max_batch=1)
-    stp = cap_p.stats(cap_p.run_schedule(burst, make))
-    log(f"  capacity, one sweep per plain call: {stp['points_per_s']:.3e} points/s")
-    ex_p.close()
-    keep = ("requests", "failed", "points_per_s", "p50_ms", "p99_ms", "max_ms", "mean_batch",
-            "max_slots_in_flight", "peak_device_bytes")
+    replay(srv, burst)   # untimed: first touches of every set and slot
+    sched = poisson_schedule(rates, args.served_seconds, seed=args.seed, n_payloads=n_pool)
+    log(f"served: {len(sched)} sweeps over {args.served_seconds:.0f}s (native server, {args.served_launch})")
+    stream_st = replay(srv, sched)
+    log(f"  p50 {stream_st['p50_ms']:.3f} ms  p99 {stream_st['p99_ms']:.3f} ms  "
+        f"{stream_st['points_per_s']:.3e} points/s  mean group {stream_st['mean_batch']}")
+    heavy = poisson_schedule([100 * r for r in rates], 3.0, seed=args.seed + 1, n_payloads=n_pool)
+    heavy_st = replay(srv, heavy)
+    log(f"  100x rates: p50 {heavy_st['p50_ms']:.3f} ms  p99 {heavy_st['p99_ms']:.3f} ms  "
+        f"{heavy_st['points_per_s']:.3e} points/s  mean group {heavy_st['mean_batch']}")
+    cap_st = replay(srv, burst)
+    log(f"  capacity: {cap_st['points_per_s']:.3e} points/s ({len(burst)} sweeps at once, "
+        f"mean group {cap_st['mean_batch']})")
+    stats = srv.stats()
+    srv.close()
+    srv_p = NativeServer(geos, n_slots=3, max_batch=1, launch="plain", sets_per_sensor=24, budget_bytes=budget,
+                         timeout_s=1.0)
+    replay(srv_p, burst)
+    plain_st = replay(srv_p, burst)
+    log(f"  capacity, one sweep per plain call: {plain_st['points_per_s']:.3e} points/s")
+    srv_p.close()
     return {"workload": "8 sensors, rings 16/32/64/128, azimuth 1024/2048/4096, 10-20 Hz Poisson, "
-                        f"{args.served_seconds:.0f}s, budget 1 GiB, 3 slots, {args.served_launch} launches, "
-                        "1 s watchdog per group",
-            **{k: (round(st[k], 3) if isinstance(st[k], float) else st[k]) for k in keep},
-            "latency": "host arrival to labels/vertex_point/counts in pinned host memory",
-            "capacity_points_per_s": round(stc["points_per_s"], 1),
-            "capacity_mean_batch": round(stc["mean_batch"], 2),
-            "capacity_plain_one_sweep_per_call_points_per_s": round(stp["points_per_s"], 1)}
+                        f"{args.served_seconds:.0f}s, budget 1 GiB, 3 slots, groups of up to 64, "
+                        f"{args.served_launch} launches, 1 s watchdog per group; native server and replay",
+            **stream_st,
+            "latency": "submission to labels/vertex_point/counts in pinned host memory",
+            "heavy_100x_rates_3s": heavy_st,
+            "capacity_points_per_s": cap_st["points_per_s"],
+            "capacity_mean_batch": cap_st["mean_batch"],
+            "capacity_plain_one_sweep_per_call_points_per_s": plain_st["points_per_s"],
+            "max_slots_in_flight": stats["max_slots_busy"], "peak_admitted_bytes": stats["peak_bytes"],
+            "server_device_bytes": stats["device_bytes"]}
 
 
 def mean_scores(outs, lp):
@@ -215,6 +232,90 @@ def paper_shape_timing(lp, synth, torch, ctx, stream, reps=50):
             "intervals": res}
 
 
+# The single-sweep configurations timed beside the batch: (name, workload, sampling interval s)
+CONFIGS = (("C1", "c1_16x1800", 1), ("C2", "c2_64x2048", 1), ("C2", "c2_64x2048", 2),
+           ("C2", "c2_64x2048", 4), ("C4", "c4_128x4096", 2))
+
+
+def path_bytes(N, V, T):
+    """Algorithmic bytes of the whole path: xyz of every input point in; vertices,
+    normals, labels, vertex_point and triangles out."""
+    return 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T
+
+
+def config_legs(lp, synth, torch, reps=200, lat_reps=100, oracle_runs=2, use_oracle=True):
+    """Each single-sweep configuration on its own, one sweep per call, inputs
+    resident in HBM, in the plain form (one kernel chain) and as a graph replay:
+    points/s of calls enqueued back to back (host clock), the GPU time of each
+    call (HIP events on the launch stream, p50/p99), the latency of one call at a
+    time (host call until its stream has finished, p50/p99), the algorithmic
+    bytes over the GPU time as a fraction of the HBM peak, and the oracle's
+    points/s on one host thread for the same sweep."""
+    import numpy as np
+    from paper_2005_02704_amd import autotune
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2))
+    res = {}
+    for cname, wname, s in CONFIGS:
+        f = synth.workload_frames(wname)[0]
+        g = lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, s, 1, f.sensor.az0)
+        ctx = lp.LidarContext(0)
+        shape = autotune.apply(ctx, [g])
+        out = lp.Outputs(g, dev)
+        prep = ctx.prepare([(torch.from_numpy(f.xyz).to(dev), g, None)], params, [out])
+        N = int(f.n_points)
+        key = f"{cname}_{f.sensor.n_rings}x{f.sensor.n_azimuth}_s{s}"
+        row = {"points": N, "launch_shape": shape}
+        for launch in ("plain", "graph"):
+            for _ in range(10):
+                ctx.lidar_mesh_segment(prep, stream, launch)
+            torch.cuda.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            t0 = time.perf_counter()
+            for a, b in evs:
+                a.record(stream)
+                ctx.lidar_mesh_segment(prep, stream, launch)
+                b.record(stream)
+            torch.cuda.synchronize()
+            wall_ms = (time.perf_counter() - t0) * 1e3 / reps
+            gpu = np.array([a.elapsed_time(b) for a, b in evs])
+            lat = []
+            for _ in range(lat_reps):
+                t = time.perf_counter()
+                ctx.lidar_mesh_segment(prep, stream, launch)
+                stream.synchronize()
+                lat.append((time.perf_counter() - t) * 1e3)
+            V, T, K = (int(x) for x in out.counts.cpu())
+            gpu_mean = float(gpu.mean())
+            alg = path_bytes(N, V, T)
+            row[launch] = {"points_per_s": round(N / (wall_ms * 1e-3), 1),
+                           "gpu_points_per_s": round(N / (gpu_mean * 1e-3), 1),
+                           "gpu_ms_p50": round(float(np.percentile(gpu, 50)), 5),
+                           "gpu_ms_p99": round(float(np.percentile(gpu, 99)), 5),
+                           "latency_ms_p50": round(float(np.percentile(lat, 50)), 5),
+                           "latency_ms_p99": round(float(np.percentile(lat, 99)), 5),
+                           "algorithmic_gbs": round(alg / (gpu_mean * 1e-3) / 1e9, 1),
+                           "frac_of_hbm_peak": round(alg / (gpu_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            row.update(vertices=V, triangles=T, segments=K, algorithmic_bytes=alg)
+        if use_oracle:
+            import oracle
+            best = None
+            for _ in range(oracle_runs):
+                t = time.perf_counter()
+                oracle.mesh_segment_frame(f, s=s)
+                el = time.perf_counter() - t
+                best = el if best is None else min(best, el)
+            row["oracle_1_thread_points_per_s"] = round(N / best, 1)
+        ctx.close()
+        res[key] = row
+        log(f"  {key}: plain {row['plain']['points_per_s']:.3e} points/s (GPU p50 {row['plain']['gpu_ms_p50']:.4f} ms, "
+            f"latency p99 {row['plain']['latency_ms_p99']:.4f} ms); graph {row['graph']['points_per_s']:.3e} points/s")
+    return {"note": "one sweep per call, inputs resident in HBM; latency = host call until the stream has finished; "
+                    "algorithmic bytes = 12 N + 32 V + 12 T over the mean GPU time of a call",
+            "configs": res}
+
+
 def rocm_version():
     """The ROCm release the library was built against, as installed."""
     try:
@@ -252,12 +353,14 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="workgroups per batched stage, 0 = library default")
     ap.add_argument("--served-launch", default="graph", choices=("graph", "batched"),
                     help="launch form of the served run's groups")
-    ap.add_argument("--served-seconds", type=float, default=10.0,
+    ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
     ap.add_argument("--in-flight", type=int, default=2,
                     help="also time the batched form with this many batches in flight (1 = skip)")
     ap.add_argument("--forms", default="graph,batched,plain",
                     help="launch forms to time (graph is always timed: it gives value)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the single-sweep configurations (16x1800; 64x2048 at s = 1, 2, 4; 128x4096 at s = 2)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the edge-score leg and the timing at the paper's sweep shape")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -365,6 +468,7 @@ def main():
             autotune.set_shape(c2, if_shape)
             o2 = [lp.Outputs(g, dev) for g in geos]
             extra.append((c2, c2.prepare(inputs, params, o2), torch.cuda.Stream(dev), o2))
+        torch.cuda.synchronize()   # the new outputs' fills are done before the lanes' streams use them
         ms = run("batched", args.steps, args.warmup, [(c2, p2, s2) for c2, p2, s2, _ in extra], name)
         same = all(torch.equal(a.labels, b.labels) and torch.equal(a.counts, b.counts)
                    for c2, p2, s2, o2 in extra for a, b in zip(outs, o2))
@@ -411,8 +515,16 @@ def main():
     # launches, or batched launches with several batches in flight)
     best = max((f for f in forms if f != "plain"), key=lambda f: forms[f]["points_per_s"])
     ms_best = forms[best]["ms_per_step"]
-    alg_path = 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T   # whole path, as in the byte model
+    alg_path = path_bytes(N, V, T)
     path_gbs = alg_path / (ms_best * 1e-3) / 1e9
+    roofline["path"] = {"algorithmic_bytes_per_step": alg_path, "ms_per_step": round(ms_best, 5),
+                        "achieved": round(path_gbs, 1), "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                        "launch": best}
+
+    configs = None
+    if not args.no_configs:
+        log("single-sweep configurations")
+        configs = config_legs(lp, synth, torch, use_oracle=not args.no_cpu_baseline)
 
     accuracy = paper_timing = None
     if not args.no_accuracy:
@@ -487,6 +599,7 @@ def main():
         "vertices_per_s": round(V / (ms_best * 1e-3), 1),
         "path_algorithmic_gbs": round(path_gbs, 1),
         "roofline": roofline,
+        "single_sweep": configs,
         "served": served,
         "accuracy": accuracy,
         "paper_shape_timing": paper_timing,

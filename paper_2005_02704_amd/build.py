@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblidarseg.so")
-SOURCES = ["lidarseg_kernels.hip", "lidarseg_api.hip"]
+SOURCES = ["lidarseg_kernels.hip", "lidarseg_api.hip", "lidarseg_serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1021,6 +1021,45 @@ int mesh_call_noalloc(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frame
 
 }  // namespace
 
+int lidarseg::ctx_reserve(lidar_ctx* c, const lidar_sensor_t* sensors, int32_t n_sensors, int32_t max_frames,
+                          uint64_t budget, const uint64_t* bytes_per_sensor, bool plain, hipStream_t stream) {
+    if (!c || !sensors || n_sensors < 1 || max_frames < 1 || !bytes_per_sensor) return LIDAR_EINVAL;
+    // Each total is at most max_frames times its largest per-sweep value, and at
+    // most the budget times its largest value per byte of a sweep.
+    constexpr int NQ = 5;  // cells, tiles, labelling items, border slots, rings
+    int64_t most[NQ] = {0, 0, 0, 0, 0};
+    double per_byte[NQ] = {0, 0, 0, 0, 0};
+    for (int s = 0; s < n_sensors; ++s) {
+        std::string msg;
+        const int rc = validate_sensor(&sensors[s], msg);
+        if (rc) return c->fail(rc, "sensor " + std::to_string(s) + ": " + msg);
+        const int H = sensors[s].n_rings, Wp = sensors[s].n_azimuth / sensors[s].subsample;
+        const int TW = tile_width(H, c->tile_cells);
+        const int64_t cells = (int64_t)H * Wp, tiles = (Wp + TW - 1) / TW;
+        const int64_t q[NQ] = {cells, tiles, (cells + VITEM - 1) / VITEM, tiles * 2 * H, H};
+        for (int k = 0; k < NQ; ++k) {
+            most[k] = std::max(most[k], q[k]);
+            if (bytes_per_sensor[s] > 0) per_byte[k] = std::max(per_byte[k], (double)q[k] / (double)bytes_per_sensor[s]);
+        }
+    }
+    int64_t cap[NQ];
+    for (int k = 0; k < NQ; ++k) {
+        // plain launches run the frames one after another on one frame's workspace
+        cap[k] = (plain ? 1 : (int64_t)max_frames) * most[k];
+        if (budget > 0 && per_byte[k] > 0.0) cap[k] = std::min<int64_t>(cap[k], (int64_t)((double)budget * per_byte[k]) + most[k]);
+    }
+    CallTotals tot;
+    tot.cells = cap[0];
+    tot.tiles = cap[1];
+    tot.vitems = cap[2];
+    tot.border_slots = cap[3];
+    tot.table_bytes = std::max(align_up(sizeof(BatchHeader) + sizeof(FrameDesc) * (size_t)max_frames, 8) + 8 * (size_t)cap[4],
+                               (size_t)max_frames * align_up(sizeof(BatchHeader) + sizeof(FrameDesc) + 8 * (size_t)LIDAR_MAX_RINGS, 256));
+    const hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return c->hip_fail(e, "hipSetDevice");
+    return ensure_capacity(c, tot, stream);
+}
+
 extern "C" {
 
 int lidar_mesh_segment(lidar_ctx* c, const lidar_frame_t* frames, int32_t n_frames,

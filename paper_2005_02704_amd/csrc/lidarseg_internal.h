@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lidarseg.h"
+
 namespace lidarseg {
 
 constexpr uint64_t KEY_EMPTY = ~0ull;
@@ -121,5 +123,13 @@ hipError_t fill_keys_empty(uint64_t* keys, int64_t n, hipStream_t stream);
 // event is recorded before the first kernel and after each kernel.
 hipError_t launch_chain(const BatchHeader* d_hdr, const Workspace& ws, const LaunchCfg& cfg,
                         hipStream_t stream, hipEvent_t* stage_events = nullptr);
+
+// Grows ctx's workspace up front so that no call of at most max_frames
+// sweeps of these sensors whose device bytes (bytes_per_sensor[s] each) sum to
+// at most budget (0 = no budget) has to grow it later, in the batched and graph
+// forms or (plain) in the plain form.  Growth waits for the device, which a
+// server must not do while it serves.
+int ctx_reserve(lidar_ctx* ctx, const lidar_sensor_t* sensors, int32_t n_sensors, int32_t max_frames,
+                uint64_t budget, const uint64_t* bytes_per_sensor, bool plain, hipStream_t stream);
 
 }  // namespace lidarseg

@@ -10,18 +10,20 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "lidarseg.h")).read()
+def _declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(lidar_\w+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
     import paper_2005_02704_amd as lp
+    from paper_2005_02704_amd.lidarserve import SERVE_EXPORTS
     L = lp.load_library()
-    declared = _declared()
-    assert set(declared) == set(lp.EXPORTS)
-    for name in declared:
+    assert set(_declared("lidarseg.h")) == set(lp.EXPORTS)
+    assert set(_declared("lidarserve.h")) == set(SERVE_EXPORTS)
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["lidarseg.h", "lidarserve.h"]
+    for name in list(lp.EXPORTS) + list(SERVE_EXPORTS):
         assert hasattr(L, name), name
 
 
@@ -48,7 +50,9 @@ def test_binding_structs_match_the_header(tmp_path):
     compiler's for include/lidarseg.h."""
     import subprocess
     from paper_2005_02704_amd import lidarseg as b
-    structs = [b.lidar_sensor_t, b.lidar_frame_t, b.lidar_params_t, b.lidar_result_t]
+    from paper_2005_02704_amd import lidarserve as sv
+    structs = [b.lidar_sensor_t, b.lidar_frame_t, b.lidar_params_t, b.lidar_result_t, sv.lidar_server_opts_t,
+               sv.lidar_served_t, sv.lidar_server_result_t, sv.lidar_server_stats_t]
     lines = []
     for st in structs:
         name = st.__name__
@@ -56,7 +60,8 @@ def test_binding_structs_match_the_header(tmp_path):
         for fname, _ in st._fields_:
             lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
     src = tmp_path / "layout.c"
-    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lidarseg.h\"\nint main(void) {\n"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lidarseg.h\"\n#include \"lidarserve.h\"\n"
+                   "int main(void) {\n"
                    + "\n".join(lines) + "\nreturn 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
@@ -92,17 +97,21 @@ def test_binding_constants_match_the_header():
     import subprocess
     import tempfile
     import paper_2005_02704_amd as lp
+    from paper_2005_02704_amd import lidarserve as sv
     names = ["LIDAR_OK", "LIDAR_EINVAL", "LIDAR_ENOMEM", "LIDAR_EDEVICE", "LIDAR_MAX_RINGS", "LIDAR_LAUNCH_PLAIN",
              "LIDAR_LAUNCH_BATCHED", "LIDAR_LAUNCH_GRAPH", "LIDAR_PRED_COMPONENTS", "LIDAR_PRED_COSINE",
              "LIDAR_MAX_SCORE_RADIUS", "LIDAR_N_STAGES", "LIDAR_NOALLOC_SCRATCH_BYTES", "LIDAR_NOALLOC_MAX_FRAMES"]
-    body = "\n".join(f'printf("{n} %lld\\n", (long long)({n}));' for n in names)
+    served = ["LIDAR_SERVED_OK", "LIDAR_SERVED_TIMED_OUT", "LIDAR_SERVED_FAILED"]
+    body = "\n".join(f'printf("{n} %lld\\n", (long long)({n}));' for n in names + served)
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "consts.c")
         exe = os.path.join(d, "consts")
-        open(src, "w").write("#include <stdio.h>\n#include \"lidarseg.h\"\nint main(void) {\n" + body +
+        open(src, "w").write("#include <stdio.h>\n#include \"lidarserve.h\"\nint main(void) {\n" + body +
                              "\nreturn 0;\n}\n")
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
         out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
     got = dict(line.split() for line in out if line)
     for n in names:
         assert int(got[n]) == getattr(lp, n), n
+    for n in served:
+        assert int(got[n]) == getattr(sv, n), n

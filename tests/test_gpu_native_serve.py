@@ -1,0 +1,132 @@
+"""The native served form (include/lidarserve.h) on the GPU: a Poisson mix of
+sweeps from several sensors, submitted while other groups run, comes back with
+every result equal (bit for bit) to the same sweep run alone through
+lidar_mesh_segment; groups overlap and batch; refusals and the watchdog's
+bookkeeping hold; the replay driver serves a schedule."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pool():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_02704_amd as lp
+    sensors = [s for s, _ in synth.served_sensors(8)][:5]
+    frames = [[synth.make_frame(s, "street", 700 + 10 * q + k, sigma=0.01, dropout=0.1) for k in range(2)]
+              for q, s in enumerate(sensors)]
+    geos = [lp.SensorGeometry(s.elevations(), s.n_azimuth, 1, 1, s.az0) for s in sensors]
+    pinned = [[torch.from_numpy(f.xyz).pin_memory() for f in row] for row in frames]
+    ctx = lp.LidarContext(0)
+    alone = {}
+    for q in range(len(sensors)):
+        for k in range(2):
+            x = torch.from_numpy(frames[q][k].xyz).cuda()
+            o = lp.lidar_mesh_segment(ctx, [(x, geos[q], None)], launch="plain")[0].trimmed()
+            alone[(q, k)] = {key: (v.cpu().numpy() if hasattr(v, "cpu") else v) for key, v in o.items()}
+    torch.cuda.synchronize()
+    ctx.close()
+    return geos, pinned, alone
+
+
+@pytest.mark.parametrize("launch,max_batch", [("graph", 8), ("batched", 8), ("plain", 1)])
+def test_native_served_mix_equals_alone(pool, launch, max_batch):
+    from paper_2005_02704_amd.lidarserve import LIDAR_SERVED_OK, NativeServer
+    from paper_2005_02704_amd.serve import poisson_schedule
+    geos, pinned, alone = pool
+    srv = NativeServer(geos, n_slots=3, max_batch=max_batch, launch=launch, sets_per_sensor=12,
+                       budget_bytes=1 << 30, copy_mesh=True)
+    try:
+        sched = poisson_schedule([400.0] * len(geos), 0.25, seed=11, n_payloads=2)
+        print(f"{launch}: serving {len(sched)} requests", flush=True)
+        which, results, done = {}, {}, []
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(sched) or len(done) < len(sched):
+            now = time.perf_counter() - t0
+            while i < len(sched) and sched[i][0] <= now:
+                _, q, k = sched[i]
+                which[srv.submit(q, pinned[q][k])] = (q, k)
+                i += 1
+            for d in srv.poll():
+                done.append(d)
+                assert d["status"] == LIDAR_SERVED_OK, d
+                results[d["id"]] = srv.result(d["id"])
+                srv.release(d["id"])
+            time.sleep(1e-4)
+        st = srv.stats()
+        print(st, flush=True)
+        assert st["admitted"] == len(sched) and st["timed_out"] == 0 and st["failed"] == 0
+        sizes = [d["group_size"] for d in done]
+        if max_batch > 1:
+            assert st["max_slots_busy"] >= 2 and np.mean(sizes) > 1.0
+        else:
+            assert max(sizes) == 1
+        for rid, res in results.items():
+            ref = alone[which[rid]]
+            assert res["counts"] == ref["counts"], (rid, which[rid])
+            for key in ("labels", "vertex_point", "vertices", "normals", "triangles"):
+                a, b = res[key], ref[key]
+                if key in ("vertices", "normals"):
+                    a, b = a.view(np.uint32), b.view(np.uint32)
+                assert np.array_equal(a, b), (rid, key)
+        lat = np.array([d["t_done"] - d["t_arrival"] for d in done])
+        assert (lat > 0).all()
+    finally:
+        srv.close()
+
+
+def test_native_server_refusals_and_release(pool):
+    import paper_2005_02704_amd as lp
+    from paper_2005_02704_amd.lidarserve import NativeServer
+    geos, pinned, alone = pool
+    with pytest.raises(lp.LidarError):
+        NativeServer(geos, n_slots=0)
+    srv = NativeServer(geos, n_slots=1, max_batch=4, launch="batched", sets_per_sensor=2, budget_bytes=1 << 30)
+    try:
+        rays = geos[0].n_rings * geos[0].n_azimuth
+        with pytest.raises(lp.LidarError):
+            srv.submit(0, pinned[0][0], rays + 1)       # more points than the sensor has rays
+        with pytest.raises(lp.LidarError):
+            srv.submit(len(geos), pinned[0][0])          # no such sensor
+        rid = srv.submit(0, pinned[0][0])
+        t0 = time.perf_counter()
+        got = []
+        while not got and time.perf_counter() - t0 < 30:
+            got = srv.poll()
+            time.sleep(1e-3)
+        assert got and got[0]["id"] == rid
+        r = srv.result(rid)
+        assert r["counts"] == alone[(0, 0)]["counts"]
+        srv.release(rid)
+        with pytest.raises(lp.LidarError):
+            srv.release(rid)                              # released once
+        with pytest.raises(lp.LidarError):
+            srv.result(rid)
+    finally:
+        srv.close()
+
+
+def test_native_replay_serves_a_schedule(pool):
+    from paper_2005_02704_amd.lidarserve import LIDAR_SERVED_OK, NativeServer
+    from paper_2005_02704_amd.serve import poisson_schedule
+    geos, pinned, alone = pool
+    srv = NativeServer(geos, n_slots=3, max_batch=16, launch="graph", sets_per_sensor=16, budget_bytes=1 << 30)
+    try:
+        sched = poisson_schedule([200.0] * len(geos), 0.5, seed=3, n_payloads=2)
+        lat, status, gsize, wall = srv.replay([t for t, _, _ in sched], [q for _, q, _ in sched],
+                                              [pinned[q][k] for _, q, k in sched])
+        print(f"replay: {len(sched)} sweeps in {wall:.3f}s, p50 {np.percentile(lat, 50) * 1e3:.2f} ms, "
+              f"p99 {np.percentile(lat, 99) * 1e3:.2f} ms, mean group {gsize.mean():.2f}", flush=True)
+        assert (status == LIDAR_SERVED_OK).all()
+        assert wall >= sched[-1][0]
+        assert (lat > 0).all() and lat.max() < 5.0
+    finally:
+        srv.close()
