@@ -91,9 +91,10 @@ void lidar_server_destroy(lidar_server* srv);
 const char* lidar_server_last_error(const lidar_server* srv);
 
 /* Queues one sweep of sensor `sensor`: xyz host [n_points][3] FP32 (pinned
- * memory lets the copy overlap; it must stay valid until the request is
- * reported finished), 0 <= n_points <= n_rings * n_azimuth.  Writes the
- * request id. */
+ * memory lets the copy overlap), 0 <= n_points <= n_rings * n_azimuth.  The
+ * points must stay valid until the request is reported finished, and, for a
+ * request reported LIDAR_SERVED_TIMED_OUT (whose group may still be running),
+ * until lidar_server_destroy.  Writes the request id. */
 int lidar_server_submit(lidar_server* srv, int32_t sensor, const float* xyz, int64_t n_points,
                         int64_t* id);
 /* Writes up to max finished requests (in completion order) and their number. */

@@ -85,7 +85,7 @@ public:
                     } else {
                         r.status = ST_SERVED;
                         r.t_done = now;
-                        done_.push_back(id);
+                        done_.push_back(r);
                     }
                 }
                 in_use_ -= sl.bytes;
@@ -97,7 +97,7 @@ public:
                     Request& r = reqs_[id];
                     r.status = ST_TIMED_OUT;
                     r.t_done = now;
-                    done_.push_back(id);
+                    done_.push_back(r);
                     ++timed_out_;
                 }
                 sl.abandoned = true;
@@ -149,7 +149,8 @@ public:
                     r.set = -1;
                     r.status = ST_FAILED;
                     r.t_done = now;
-                    done_.push_back(id);
+                    done_.push_back(r);
+                    reqs_.erase(id);  // nothing held: forgotten at once
                     ++failed_;
                 }
                 in_use_ -= sl.bytes;
@@ -160,17 +161,15 @@ public:
         return changes;
     }
 
-    // Moves up to `max` finished requests (served, timed out or failed) into `out`.
+    // Moves up to `max` finished requests (served, timed out or failed), as they
+    // were when they finished, into `out`.  A report does not depend on the
+    // request's record, which a timed-out request loses when its device work ends.
     int take_done(Request* out, int max) {
         std::lock_guard<std::mutex> lock(mu_);
         int n = 0;
         while (n < max && !done_.empty()) {
-            const int64_t id = done_.front();
+            out[n++] = done_.front();
             done_.pop_front();
-            auto it = reqs_.find(id);
-            if (it == reqs_.end()) continue;
-            out[n++] = it->second;
-            if (it->second.status == ST_FAILED) reqs_.erase(it);  // nothing held: forgotten at once
         }
         return n;
     }
@@ -234,7 +233,7 @@ private:
     std::mutex mu_;
     std::unordered_map<int64_t, Request> reqs_;
     std::deque<int64_t> waiting_;
-    std::deque<int64_t> done_;
+    std::deque<Request> done_;  // finished requests not yet taken, as they finished
     int64_t next_id_ = 0;
     uint64_t in_use_ = 0, peak_in_use_ = 0;
     int64_t groups_ = 0, admitted_ = 0, timed_out_ = 0, failed_ = 0;

@@ -79,8 +79,9 @@ class NativeServer:
     """A lidar_server: the continuous-batching server of liblidarseg.
 
     sensors: [SensorGeometry]; requests name a sensor by index.  Host points
-    given to submit() must stay alive (and should be pinned) until the request
-    is reported finished by poll()."""
+    given to submit() should be pinned; the binding holds them until poll()
+    reports the request finished (until close() for a request that timed out,
+    whose group may still read them)."""
 
     def __init__(self, sensors, device: int = 0, params=None, n_slots: int = 3, max_batch: int = 64,
                  launch: str = "graph", sets_per_sensor: int = 16, budget_bytes: int = 1 << 30,
@@ -102,13 +103,15 @@ class NativeServer:
         if rc != LIDAR_OK:
             raise LidarError(rc, self._L.lidar_server_last_error(None).decode())
         self.copy_mesh = copy_mesh
-        self._held = {}   # request id -> host points kept alive until it finishes
+        self._held = {}       # request id -> host points kept alive until it finishes
+        self._abandoned = []  # points of timed-out requests: their group may still read them
 
     def close(self):
         if self._h:
             self._L.lidar_server_destroy(self._h)
             self._h = ctypes.c_void_p()
             self._held.clear()
+            self._abandoned.clear()
 
     def __del__(self):
         try:
@@ -140,7 +143,9 @@ class NativeServer:
         self._check(self._L.lidar_server_poll(self._h, buf, max_n, ctypes.byref(k)))
         out = []
         for d in buf[:k.value]:
-            self._held.pop(d.id, None)
+            pts = self._held.pop(d.id, None)
+            if d.status == LIDAR_SERVED_TIMED_OUT:
+                self._abandoned.append(pts)
             out.append(dict(id=d.id, sensor=d.sensor, status=d.status, slot=d.slot, group_size=d.group_size,
                             t_arrival=d.t_arrival, t_admit=d.t_admit, t_done=d.t_done))
         return out

@@ -369,6 +369,8 @@ SCENE_KINDS = {
     "urban": dict(n_boxes=40, n_cyl=20, n_sph=10, sloped=True, walls=False),
     # noise-free geometry checks
     "ground": dict(n_boxes=0, n_cyl=0, n_sph=0, sloped=False, walls=False),
+    # ground alone, tilted 0-8 degrees: the far rings meet it at grazing angles
+    "sloped_ground": dict(n_boxes=0, n_cyl=0, n_sph=0, sloped=True, walls=False),
     "boxes": dict(n_boxes=6, n_cyl=0, n_sph=0, sloped=False, walls=False),
     "spheres": dict(n_boxes=0, n_cyl=0, n_sph=6, sloped=False, walls=False),
     "walls": dict(n_boxes=0, n_cyl=0, n_sph=0, sloped=False, walls=True),

@@ -164,6 +164,25 @@ void watchdog() {
     CHECK(s.stats().timed_out == 2);
 }
 
+void timed_out_reports_outlive_their_records() {
+    // the watchdog fires, then the device work ends (its sets return and the
+    // records go) before anyone takes the reports: they must still be there
+    FakeExec ex(1, 2, 1);
+    lidarserve::Scheduler<FakeExec> s(ex, 1, 1000, 2, 1.0);
+    s.submit(req(0, 1));
+    s.submit(req(0, 1));
+    s.step(0.0);
+    s.step(2.0);               // overdue
+    ex.done[0] = true;
+    s.step(2.5);               // the device finishes first
+    auto d = take(s);
+    CHECK(d.size() == 2);
+    for (auto& r : d) CHECK(r.status == lidarserve::ST_TIMED_OUT && r.t_done == 2.0);
+    CHECK(ex.free_sets[0].size() == 2);
+    Request r;
+    CHECK(!s.served(0, &r) && !s.release(0));
+}
+
 void launch_failure() {
     FakeExec ex(1, 4, 1);
     lidarserve::Scheduler<FakeExec> s(ex, 1, 1000, 8, 0.0);
@@ -189,6 +208,7 @@ int main() {
     budget();
     buffer_sets();
     watchdog();
+    timed_out_reports_outlive_their_records();
     launch_failure();
     if (g_failures) {
         std::printf("%d checks failed\n", g_failures);

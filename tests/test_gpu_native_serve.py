@@ -130,3 +130,39 @@ def test_native_replay_serves_a_schedule(pool):
         assert (lat > 0).all() and lat.max() < 5.0
     finally:
         srv.close()
+
+
+def test_native_watchdog_fails_overdue_groups_and_returns_their_sets(pool):
+    """A watchdog limit far shorter than any group (1 us): groups still running
+    at the next scheduling pass fail their requests (timed out, no results).
+    The kernels run normally.  With two buffer sets per sensor, twenty sweeps
+    of one sensor can only all finish if each abandoned group's sets return to
+    the pool once its device work has ended."""
+    import paper_2005_02704_amd as lp
+    from paper_2005_02704_amd.lidarserve import LIDAR_SERVED_OK, LIDAR_SERVED_TIMED_OUT, NativeServer
+    geos, pinned, alone = pool
+    srv = NativeServer(geos, n_slots=2, max_batch=2, launch="graph", sets_per_sensor=2, budget_bytes=1 << 30,
+                       timeout_s=1e-6)
+    try:
+        ids = [srv.submit(0, pinned[0][k % 2]) for k in range(20)]
+        done, t0 = {}, time.perf_counter()
+        while len(done) < len(ids) and time.perf_counter() - t0 < 60:
+            for d in srv.poll():
+                done[d["id"]] = d
+                if d["status"] == LIDAR_SERVED_OK:
+                    srv.release(d["id"])
+            time.sleep(1e-3)
+        assert sorted(done) == sorted(ids)
+        status = [done[i]["status"] for i in ids]
+        timed_out = sum(s == LIDAR_SERVED_TIMED_OUT for s in status)
+        print(f"{timed_out} of {len(ids)} timed out", flush=True)
+        assert set(status) <= {LIDAR_SERVED_OK, LIDAR_SERVED_TIMED_OUT}
+        assert timed_out >= len(ids) // 2
+        st = srv.stats()
+        assert st["timed_out"] == timed_out and st["admitted"] == len(ids)
+        for i in ids:
+            if done[i]["status"] == LIDAR_SERVED_TIMED_OUT:
+                with pytest.raises(lp.LidarError):
+                    srv.result(i)
+    finally:
+        srv.close()
