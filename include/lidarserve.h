@@ -88,6 +88,7 @@ int lidar_server_create(int device, const lidar_sensor_t* sensors, int32_t n_sen
                         lidar_server** out);
 /* Stops the server thread after the device work in flight ends; frees everything. */
 void lidar_server_destroy(lidar_server* srv);
+/* Message of the calling thread's last failed server call (srv may be NULL). */
 const char* lidar_server_last_error(const lidar_server* srv);
 
 /* Queues one sweep of sensor `sensor`: xyz host [n_points][3] FP32 (pinned

@@ -114,8 +114,14 @@ struct Executor {
         return 0;
     }
 
-    // The group's work has ended (successfully or not: a failed query also ends the wait).
-    bool finished(int slot) { return hipEventQuery(done[slot]) != hipErrorNotReady; }
+    // 0 while the slot's group runs, 1 once it is done, -1 if its device work failed.
+    int finished(int slot) {
+        const hipError_t e = hipEventQuery(done[slot]);
+        if (e == hipErrorNotReady) return 0;
+        if (e == hipSuccess) return 1;
+        fail(std::string("group on slot ") + std::to_string(slot) + ": " + hipGetErrorString(e));
+        return -1;
+    }
 
     int fail(const std::string& msg) {
         std::lock_guard<std::mutex> lock(err_mu);
@@ -137,13 +143,12 @@ struct lidar_server {
     std::condition_variable cv;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     uint64_t budget = 0;
-    std::string err;
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
+    // Failures are reported per calling thread (any thread may call the server).
     int fail(int code, const std::string& msg) {
-        err = msg;
         g_serve_error = msg;
         return code;
     }
@@ -193,7 +198,7 @@ void free_server(lidar_server* s) {
 
 extern "C" {
 
-const char* lidar_server_last_error(const lidar_server* srv) { return srv ? srv->err.c_str() : g_serve_error.c_str(); }
+const char* lidar_server_last_error(const lidar_server*) { return g_serve_error.c_str(); }
 
 double lidar_server_now(const lidar_server* srv) { return srv ? srv->now() : 0.0; }
 

@@ -16,7 +16,8 @@
 //   bool acquire_set(int32_t sensor, int32_t* set)  a free buffer set (false: none free now)
 //   void return_set(int32_t sensor, int32_t set)
 //   int  launch(int slot, const Request* const* group, int n)  enqueue; 0 on success
-//   bool finished(int slot)                          the slot's group is done on the device
+//   int  finished(int slot)   0 while the slot's group runs, 1 once it is done, -1 once its
+//                             device work has failed (its requests fail)
 #pragma once
 
 #include <algorithm>
@@ -72,7 +73,8 @@ public:
         for (int s = 0; s < (int)slots_.size(); ++s) {
             Slot& sl = slots_[s];
             if (!sl.busy) continue;
-            if (ex_.finished(s)) {
+            const int fin = ex_.finished(s);
+            if (fin != 0) {
                 std::lock_guard<std::mutex> lock(mu_);
                 for (int64_t id : sl.group) {
                     auto it = reqs_.find(id);
@@ -82,6 +84,15 @@ public:
                         // reported as timed out already: its set returns now that the device is done
                         ex_.return_set(r.sensor, r.set);
                         reqs_.erase(it);
+                    } else if (fin < 0) {
+                        // the device work failed: no results, the set returns at once
+                        ex_.return_set(r.sensor, r.set);
+                        r.set = -1;
+                        r.status = ST_FAILED;
+                        r.t_done = now;
+                        done_.push_back(r);
+                        reqs_.erase(it);
+                        ++failed_;
                     } else {
                         r.status = ST_SERVED;
                         r.t_done = now;

@@ -24,12 +24,12 @@ int g_failures = 0;
 
 struct FakeExec {
     std::vector<std::vector<int32_t>> free_sets;  // per sensor
-    std::vector<bool> done;                       // per slot: the device finished the group
+    std::vector<int> done;                        // per slot: 0 running, 1 finished, -1 failed
     std::vector<std::vector<int64_t>> launched;   // per slot: ids of its last group
     bool fail_next = false;
     int launches = 0;
 
-    FakeExec(int n_sensors, int sets, int n_slots) : free_sets(n_sensors), done(n_slots, false), launched(n_slots) {
+    FakeExec(int n_sensors, int sets, int n_slots) : free_sets(n_sensors), done(n_slots, 0), launched(n_slots) {
         for (auto& p : free_sets)
             for (int k = 0; k < sets; ++k) p.push_back(k);
     }
@@ -44,14 +44,14 @@ struct FakeExec {
         ++launches;
         launched[slot].clear();
         for (int i = 0; i < n; ++i) launched[slot].push_back(g[i]->id);
-        done[slot] = false;
+        done[slot] = 0;
         if (fail_next) {
             fail_next = false;
             return -1;
         }
         return 0;
     }
-    bool finished(int slot) { return done[slot]; }
+    int finished(int slot) { return done[slot]; }
 };
 
 Request req(int32_t sensor, uint64_t bytes) {
@@ -76,7 +76,7 @@ void fifo_and_group_size() {
     CHECK((ex.launched[0] == std::vector<int64_t>{0, 1, 2, 3}));
     CHECK((ex.launched[1] == std::vector<int64_t>{4, 5, 6, 7}));
     CHECK(s.step(0.1) == 0);  // both slots busy
-    ex.done[0] = true;
+    ex.done[0] = 1;
     CHECK(s.step(0.2) == 2);  // slot 0 completes, then takes 8 and 9
     CHECK((ex.launched[0] == std::vector<int64_t>{8, 9}));
     auto d = take(s);
@@ -93,7 +93,7 @@ void fifo_and_group_size() {
     CHECK(s.release(0));
     CHECK(!s.release(0));  // released once
     CHECK(!s.release(5));  // still running
-    ex.done[0] = ex.done[1] = true;
+    ex.done[0] = ex.done[1] = 1;
     s.step(0.3);
     CHECK(take(s).size() == 6);
     CHECK(s.idle());
@@ -111,7 +111,7 @@ void budget() {
     // 80 bytes admitted into slot 0; the head (40 more) does not fit: nothing else is admitted
     CHECK(ex.launched[0].size() == 2 && ex.launched[1].empty() && ex.launched[2].empty());
     CHECK(s.stats().bytes_in_use == 80 && s.stats().peak_bytes == 80);
-    ex.done[0] = true;
+    ex.done[0] = 1;
     s.step(1.0);
     CHECK(ex.launched[0].size() == 2 && ex.launched[0][0] == 2);
     CHECK(s.stats().bytes_in_use == 80);
@@ -128,7 +128,7 @@ void buffer_sets() {
     s.step(0.0);
     CHECK(ex.launched[0] == std::vector<int64_t>{0});
     CHECK(ex.launched[1].empty());
-    ex.done[0] = true;
+    ex.done[0] = 1;
     s.step(0.1);
     CHECK(take(s).size() == 1);
     s.step(0.2);
@@ -156,7 +156,7 @@ void watchdog() {
     CHECK(take(s).empty());
     CHECK(ex.launches == 1);                 // request 2 waits for the slot
     CHECK(ex.free_sets[0].size() == 2);      // the timed-out group's sets are still held
-    ex.done[0] = true;                       // the device work ends
+    ex.done[0] = 1;                       // the device work ends
     s.step(2.5);
     CHECK(ex.launches == 2 && ex.launched[0] == std::vector<int64_t>{2});
     CHECK(ex.free_sets[0].size() == 3);      // two sets back, one taken by request 2
@@ -173,7 +173,7 @@ void timed_out_reports_outlive_their_records() {
     s.submit(req(0, 1));
     s.step(0.0);
     s.step(2.0);               // overdue
-    ex.done[0] = true;
+    ex.done[0] = 1;
     s.step(2.5);               // the device finishes first
     auto d = take(s);
     CHECK(d.size() == 2);
@@ -181,6 +181,26 @@ void timed_out_reports_outlive_their_records() {
     CHECK(ex.free_sets[0].size() == 2);
     Request r;
     CHECK(!s.served(0, &r) && !s.release(0));
+}
+
+void device_failure() {
+    // the device work of a group fails: its requests are reported failed, not
+    // served, and their sets return at once
+    FakeExec ex(1, 2, 1);
+    lidarserve::Scheduler<FakeExec> s(ex, 1, 1000, 2, 0.0);
+    s.submit(req(0, 1));
+    s.submit(req(0, 1));
+    s.step(0.0);
+    ex.done[0] = -1;
+    s.step(0.5);
+    auto d = take(s);
+    CHECK(d.size() == 2);
+    for (auto& r : d) CHECK(r.status == lidarserve::ST_FAILED && r.t_done == 0.5);
+    CHECK(ex.free_sets[0].size() == 2);
+    CHECK(s.stats().failed == 2 && s.stats().bytes_in_use == 0);
+    Request r;
+    CHECK(!s.served(0, &r) && !s.release(0));
+    CHECK(s.idle());
 }
 
 void launch_failure() {
@@ -209,6 +229,7 @@ int main() {
     buffer_sets();
     watchdog();
     timed_out_reports_outlive_their_records();
+    device_failure();
     launch_failure();
     if (g_failures) {
         std::printf("%d checks failed\n", g_failures);
