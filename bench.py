@@ -66,6 +66,32 @@ def stage_bytes(stage, N, V, T):
     return 0
 
 
+def link_rates(torch):
+    """Pinned host <-> device copy rates (GB/s) of the PCIe link: 8 copies of
+    64 MiB host to device, device to host, and both at once on three streams."""
+    dev = torch.device("cuda", 0)
+    chunk, count = 64 << 20, 8
+    host = [torch.empty(chunk, dtype=torch.uint8).pin_memory() for _ in range(2 * count)]
+    devm = [torch.empty(chunk, dtype=torch.uint8, device=dev) for _ in range(2 * count)]
+    streams = [torch.cuda.Stream(dev) for _ in range(3)]
+    out = {}
+    for name, pairs in (("h2d", [(devm[i], host[i]) for i in range(count)]),
+                        ("d2h", [(host[i], devm[i]) for i in range(count)]),
+                        ("both", [(devm[i], host[i]) for i in range(count)] +
+                                 [(host[count + i], devm[count + i]) for i in range(count)])):
+        def go():
+            for j, (dst, src) in enumerate(pairs):
+                with torch.cuda.stream(streams[j % 3]):
+                    dst.copy_(src, non_blocking=True)
+            torch.cuda.synchronize()
+        go()
+        t = time.perf_counter()
+        for _ in range(4):
+            go()
+        out[name + "_GB_s"] = round(chunk * len(pairs) * 4 / (time.perf_counter() - t) / 1e9, 1)
+    return out
+
+
 def served_run(args, lp, synth, torch):
     """8 simulated sensors (rings 16/32/64/128, widths 1024/2048/4096, 10-20 Hz
     Poisson arrivals) through the native continuous-batching server, driven by
@@ -74,7 +100,8 @@ def served_run(args, lp, synth, torch):
     pool with every request arriving at once (capacity), and for comparison the
     same burst served one sweep per call with plain per-frame launches.
     Latency runs from submission to the results in pinned host memory; every
-    rate includes the points' host-to-device copies and the results' copies back."""
+    rate includes the points' host-to-device copies and the results' copies back,
+    and the PCIe link's own copy rates bound the capacity."""
     import numpy as np
     from paper_2005_02704_amd.lidarserve import LIDAR_SERVED_OK, NativeServer
     from paper_2005_02704_amd.serve import poisson_schedule
@@ -85,7 +112,8 @@ def served_run(args, lp, synth, torch):
              for k in range(n_pool)] for q, (s, _) in enumerate(sensors)]
     geos = [lp.SensorGeometry(s.elevations(), s.n_azimuth, 1, 1, s.az0) for s, _ in sensors]
     pinned = [[torch.from_numpy(f.xyz).pin_memory() for f in row] for row in pool]
-    budget = 1 << 30
+    budget = 2 << 30
+    n_slots, max_batch = 4, 32
 
     def replay(srv, sched):
         lat, st, gs, wall = srv.replay([t for t, _, _ in sched], [q for _, q, _ in sched],
@@ -102,7 +130,7 @@ def served_run(args, lp, synth, torch):
                 "wall_s": round(wall, 3)}
 
     rates = [r for _, r in sensors]
-    srv = NativeServer(geos, n_slots=3, max_batch=64, launch=args.served_launch, sets_per_sensor=24,
+    srv = NativeServer(geos, n_slots=n_slots, max_batch=max_batch, launch=args.served_launch, sets_per_sensor=24,
                        budget_bytes=budget, timeout_s=1.0)
     burst = [(0.0, q % 8, (q // 8) % n_pool) for q in range(8 * 64)]
     replay(srv, burst)   # untimed: first touches of every set and slot
@@ -120,14 +148,22 @@ def served_run(args, lp, synth, torch):
         f"mean group {cap_st['mean_batch']})")
     stats = srv.stats()
     srv.close()
-    srv_p = NativeServer(geos, n_slots=3, max_batch=1, launch="plain", sets_per_sensor=24, budget_bytes=budget,
+    # bytes the burst moves over the link: points in, each sweep's result block
+    # (8 + 2 x lattice cells int32) out
+    link_bytes = sum(12 * int(pinned[q][k].shape[0]) + 4 * (8 + 2 * geos[q].n_rings * geos[q].n_azimuth)
+                     for _, q, k in burst)
+    link = link_rates(torch)
+    link["burst_bytes_per_point"] = round(link_bytes / cap_st["points"], 2)
+    link["bound_points_per_s"] = round(link["both_GB_s"] * 1e9 / link["burst_bytes_per_point"], 1)
+    log(f"  PCIe link: {link}")
+    srv_p = NativeServer(geos, n_slots=n_slots, max_batch=1, launch="plain", sets_per_sensor=24, budget_bytes=budget,
                          timeout_s=1.0)
     replay(srv_p, burst)
     plain_st = replay(srv_p, burst)
     log(f"  capacity, one sweep per plain call: {plain_st['points_per_s']:.3e} points/s")
     srv_p.close()
     return {"workload": "8 sensors, rings 16/32/64/128, azimuth 1024/2048/4096, 10-20 Hz Poisson, "
-                        f"{args.served_seconds:.0f}s, budget 1 GiB, 3 slots, groups of up to 64, "
+                        f"{args.served_seconds:.0f}s, budget {budget >> 30} GiB, {n_slots} slots, groups of up to {max_batch}, "
                         f"{args.served_launch} launches, 1 s watchdog per group; native server and replay",
             **stream_st,
             "latency": "submission to labels/vertex_point/counts in pinned host memory",
@@ -135,6 +171,7 @@ def served_run(args, lp, synth, torch):
             "capacity_points_per_s": cap_st["points_per_s"],
             "capacity_mean_batch": cap_st["mean_batch"],
             "capacity_plain_one_sweep_per_call_points_per_s": plain_st["points_per_s"],
+            "pcie_link": link,
             "max_slots_in_flight": stats["max_slots_busy"], "peak_admitted_bytes": stats["peak_bytes"],
             "server_device_bytes": stats["device_bytes"]}
 
