@@ -187,6 +187,7 @@ constexpr int RING_LUT = 1024;   // buckets of the ring lookup table (tan of ele
 template <int NT>
 __global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ hdr, Workspace ws) {
     constexpr int PPT = POINT_BLOCK / NT;  // points per thread per item
+    static_assert(PPT <= 4, "the given rings of a thread's points fit one word");
     __shared__ double s_elev[MAX_RINGS];
     __shared__ float s_T[MAX_RINGS];       // s_T[i]: tan of the midpoint of rings i and i+1 (descending)
     __shared__ uint8_t s_lut[RING_LUT];    // ring at the lower edge of each t bucket
@@ -236,32 +237,43 @@ __global__ __launch_bounds__(NT, 6) void k_bin(const BatchHeader* __restrict__ h
         unsigned long long* keys = reinterpret_cast<unsigned long long*>(ws.keys + fd->cell_off);
         const int64_t p0 = (int64_t)(b - fd->pblk_off) * POINT_BLOCK + threadIdx.x;
         const int64_t np = fd->n_points;
-        // all loads of the item first, so their latencies overlap
+        // all loads of the item first, so their latencies overlap: unconditional
+        // (a lane past the frame's last point reads that point and drops it
+        // below), since a load under a lane mask is waited for at once
         float px[PPT], py[PPT], pz[PPT];
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
             const int64_t p = p0 + r * NT;
-            px[r] = py[r] = pz[r] = __builtin_nanf("");
-            if (p < np) {
-                px[r] = xyz[3 * p];
-                py[r] = xyz[3 * p + 1];
-                pz[r] = xyz[3 * p + 2];
-            }
+            const auto q = xyz + 3 * (p < np ? p : np - 1);   // np >= 1: the item holds a point
+            px[r] = q[0];
+            py[r] = q[1];
+            pz[r] = q[2];
         }
         int32_t* const pcell = fd->point_labels ? ws.pcell + fd->pt_off : nullptr;
         const auto rings = gmem(fd->rings);   // the sensor's own ring of each point, if given
+        // the given rings of the item's points, one byte each, loaded with the
+        // points (a load inside the pass below would also wait for the atomics
+        // issued before it)
+        uint32_t given4 = 0;
+        if (rings) {
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+                const int64_t p = p0 + r * NT;
+                given4 |= (uint32_t)rings[p < np ? p : np - 1] << (8 * r);
+            }
+        }
         // fast pass: FP32 estimates; a point inside a guard band is only flagged
         uint32_t hard = 0;
 #pragma unroll
         for (int r = 0; r < PPT; ++r) {
             const int64_t p = p0 + r * NT;
             const float xf = px[r], yf = py[r], zf = pz[r];
-            bool used = isfinite(xf) && isfinite(yf) && isfinite(zf);
+            bool used = p < np && isfinite(xf) && isfinite(yf) && isfinite(zf);
             const double x = xf, y = yf, z = zf;
             const double rho2 = x * x + y * y;   // products of floats are exact in FP64
             const double r2 = rho2 + z * z;
             used = used && r2 >= rmin2 && r2 <= rmax2;
-            const int given = (used && rings) ? (int)rings[p] : -1;
+            const int given = rings ? (int)((given4 >> (8 * r)) & 0xffu) : -1;
             used = used && given < H;
             if (!used) {
                 if (pcell && p < np) pcell[p] = -1;
