@@ -850,17 +850,25 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
             s_misc[0] = ws.tile_vbase[t];  // k_geom summed the counts of the tiles before
             s_misc[1] = ws.tile_v[t];
         }
+        // (every word is loaded, a cell past the scan reading the tile's first,
+        // so that the loads of all rounds are in flight together)
+        uint64_t ow[RN];
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            const int l = threadIdx.x + NT * r;
+            const int j = l - nown;
+            const int64_t w = l < nown ? (int64_t)t * OCC_WORDS + (l >> 6)
+                            : (l < nscan && tn >= 0) ? (int64_t)tn * OCC_WORDS + (j >> 6)
+                                                     : (int64_t)t * OCC_WORDS;
+            ow[r] = ws.occ[w];
+        }
         int vid[RN];
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
             const int l = threadIdx.x + NT * r;
-            bool v = false;
-            if (l < nown) {
-                v = (ws.occ[(int64_t)t * OCC_WORDS + (l >> 6)] >> (l & 63)) & 1ull;
-            } else if (l < nscan && tn >= 0) {
-                const int j = l - nown;
-                v = (ws.occ[(int64_t)tn * OCC_WORDS + (j >> 6)] >> (j & 63)) & 1ull;
-            }
+            const int j = l - nown;
+            const bool v = l < nown ? ((ow[r] >> (l & 63)) & 1ull) != 0
+                         : (l < nscan && tn >= 0) ? ((ow[r] >> (j & 63)) & 1ull) != 0 : false;
             const uint64_t bv = __ballot(v);
             vid[r] = v ? lanes_below(bv) : -1;
             if (lane == 0) s_cnt[r * NW + wv] = __popcll(bv);
@@ -869,8 +877,23 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
         const int vbase = s_misc[0], own_v = s_misc[1];
         number_cells<NT, RN>(vid, s_cnt, vbase, last_tile ? 0 : vbase + own_v, own_v, nown, lane, wv);
 
-        // 2. normals by vertex id
+        // 2. normals by vertex id (all rounds' loads in flight together: a cell
+        //    without a vertex reads vertex 0's, which exists when any vertex of
+        //    the frame does, and drops it)
         const auto nrm = gmem(fd->normals);
+        float gx[RN], gy[RN], gz[RN];
+        if (fd->counts[0] > 0) {
+#pragma unroll
+            for (int r = 0; r < RN; ++r) {
+                const auto q = nrm + 3 * (int64_t)max(vid[r], 0);
+                gx[r] = q[0];
+                gy[r] = q[1];
+                gz[r] = q[2];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RN; ++r) gx[r] = gy[r] = gz[r] = 0.0f;
+        }
 #pragma unroll
         for (int r = 0; r < RN; ++r) {
             const int l = threadIdx.x + NT * r;
@@ -878,8 +901,7 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_cc(const Batch
             const float q = __builtin_nanf("");
             float ax = q, ay = q, az = q;
             if (vid[r] >= 0) {
-                const float x = nrm[3 * (int64_t)vid[r]], y = nrm[3 * (int64_t)vid[r] + 1],
-                            z = nrm[3 * (int64_t)vid[r] + 2];
+                const float x = gx[r], y = gy[r], z = gz[r];
                 if (!(x == 0.0f && y == 0.0f && z == 0.0f)) { ax = x; ay = y; az = z; }
             }
             sn3[3 * l] = ax;
@@ -1108,7 +1130,8 @@ __device__ __forceinline__ int gather_joins(const FrameDesc* fd, int t, const in
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
         const int j = lane + 64 * r;
-        ab[r] = j < ns ? slots[j] : make_int2(-1, -1);
+        ab[r] = slots[min(j, ns - 1)];   // unconditional, so the loads overlap
+        if (j >= ns) ab[r] = make_int2(-1, -1);
     }
     int n = 0;
 #pragma unroll
@@ -1130,7 +1153,10 @@ __global__ __launch_bounds__(NT) void k_merge(const BatchHeader* __restrict__ hd
     __shared__ int2 s_j[NW][2 * MAX_RINGS];
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int lane = lane_id();
+    // the wave's tile index is uniform: held in scalar registers, so the frame
+    // search and the frame's fields are scalar loads
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int* const P = ws.forest;
     for (int t = blockIdx.x * NW + wv; t < hdr->total_tiles; t += gridDim.x * NW) {
         const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
@@ -1154,7 +1180,10 @@ __global__ __launch_bounds__(NT) void k_compress(const BatchHeader* __restrict__
     __shared__ int2 s_j[NW][2 * MAX_RINGS];
     const FrameDesc* F = frames_of(hdr);
     const int nf = hdr->n_frames;
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int lane = lane_id();
+    // the wave's tile index is uniform: held in scalar registers, so the frame
+    // search and the frame's fields are scalar loads
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int* const P = ws.forest;
     for (int t = blockIdx.x * NW + wv; t < hdr->total_tiles; t += gridDim.x * NW) {
         const FrameDesc* fd = F + frame_of<&FrameDesc::tile_off>(F, nf, t);
@@ -1312,16 +1341,21 @@ __global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ 
         const int v0 = lb * VITEM;
         const int64_t wframe = (int64_t)fd->vitem_off * VITEM_WORDS;
         const int32_t* const ibase = ws.vitem_roots + fd->vitem_off;
+        // Loads of every round are issued before any is used, unconditionally
+        // (a slot past the last vertex reads the frame's first forest entry, or
+        // first root word, and drops it), so that their latencies overlap.
         int cur[RV];
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+            const int v = v0 + r * NT + threadIdx.x;
+            cur[r] = P[base + (v < V ? v : 0)];
+        }
         uint32_t walking = 0;
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int v = v0 + r * NT + threadIdx.x;
-            cur[r] = -1;
-            if (v < V) {
-                cur[r] = P[base + v];
-                if (cur[r] != base + v) walking |= 1u << r;
-            }
+            if (v >= V) cur[r] = -1;
+            else if (cur[r] != base + v) walking |= 1u << r;
         }
         for (int it = 0; walking && it < WALK_LIMIT; ++it) {
             int nxt[RV];
@@ -1333,15 +1367,25 @@ __global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ 
                 cur[r] = nxt[r];
             }
         }
+        uint64_t rbits[RV];
+        int rbase[RV];
+        uint32_t rpre[RV];
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+            const int root = cur[r] >= 0 ? cur[r] - base : 0;
+            const int64_t w = wframe + (root >> 6);
+            rbits[r] = ws.rootbits[w];
+            rbase[r] = ibase[root / VITEM];
+            rpre[r] = ws.wprefix[w];
+        }
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int v = v0 + r * NT + threadIdx.x;
             int lab = -1;
             if (v < V) {
                 const int root = cur[r] - base;
-                const int64_t w = wframe + (root >> 6);
-                const uint64_t below = ws.rootbits[w] & ((1ull << (root & 63)) - 1ull);
-                lab = 1 + ibase[root / VITEM] + (int)ws.wprefix[w] + __popcll(below);
+                const uint64_t below = rbits[r] & ((1ull << (root & 63)) - 1ull);
+                lab = 1 + rbase[r] + (int)rpre[r] + __popcll(below);
                 gmem(fd->labels)[v] = lab;
             }
             if (fd->min_seg > 1) {
