@@ -394,6 +394,9 @@ def main():
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
     ap.add_argument("--in-flight", type=int, default=2,
                     help="also time the batched form with this many batches in flight (1 = skip)")
+    ap.add_argument("--in-flight-shape", default="",
+                    help='launch shape of the batches in flight, as JSON ({"grid": G, "tile_cells": C, '
+                         '"tile_threads": T, "stage_grids": {stage: G}}); default: the autotuned table')
     ap.add_argument("--forms", default="graph,batched,plain",
                     help="launch forms to time (graph is always timed: it gives value)")
     ap.add_argument("--no-configs", action="store_true",
@@ -445,7 +448,14 @@ def main():
         from paper_2005_02704_amd import autotune
         shape = autotune.apply(ctx, geos)
         shape_src = f"autotuned table, class {autotune.batch_class(geos)}"
-    if_shape, n_flight = shape, args.in_flight
+    n_flight = args.in_flight
+    if args.in_flight_shape:
+        if_shape = json.loads(args.in_flight_shape)
+        if_shape.setdefault("stage_grids", {})
+    elif shape_src == "command line":
+        if_shape = shape
+    else:
+        if_shape = autotune.lookup_in_flight(geos)
     log(f"launch shape {shape} ({shape_src})")
     inputs = [(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)]
     outs = [lp.Outputs(g, dev) for g in geos]

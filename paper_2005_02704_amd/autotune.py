@@ -15,6 +15,13 @@ favour big tiles, many narrow ones more workgroups.  This module
   * keeps the winners in a JSON table (`tune_table.json` next to this file),
   * and looks a batch's shape up in that table.
 
+A class may also carry an "in_flight" shape, used when several batches of it
+run at once on their own contexts and streams: there each stage shares the GPU
+with the other batch's stages, and fewer workgroups per stage overlap better.
+Those entries are measured one shape per process with
+`bench.py --in-flight-shape` (the tuner here times one context only) and are
+kept when the table is rebuilt.
+
 Run `python -m paper_2005_02704_amd.autotune` on the GPU to rebuild the table
 for the standard synthetic workloads.
 """
@@ -64,6 +71,19 @@ def lookup(geometries, table: dict | None = None) -> dict:
     entry = table.get(batch_class(geometries))
     if not entry:
         return {**DEFAULT, "stage_grids": {}}
+    shape = {k: int(entry[k]) for k in ("grid", "tile_cells", "tile_threads")}
+    shape["stage_grids"] = {k: int(v) for k, v in entry.get("stage_grids", {}).items()}
+    return shape
+
+
+def lookup_in_flight(geometries, table: dict | None = None) -> dict:
+    """Shape for several batches of this class in flight at once (each on its
+    own context and stream): the class's "in_flight" entry when it has one,
+    else its one-batch shape."""
+    table = load_table() if table is None else table
+    entry = (table.get(batch_class(geometries)) or {}).get("in_flight")
+    if not entry:
+        return lookup(geometries, table)
     shape = {k: int(entry[k]) for k in ("grid", "tile_cells", "tile_threads")}
     shape["stage_grids"] = {k: int(v) for k, v in entry.get("stage_grids", {}).items()}
     return shape
@@ -191,6 +211,7 @@ def main(argv=None):
     ctx = lp.LidarContext(0)
     params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2))
     classes = {}
+    previous = load_table(args.out)
     for name, frames in _workloads():
         s = synth.WORKLOADS[name]["s"][0] if name in synth.WORKLOADS else 1
         geos = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, s, 1, f.sensor.az0) for f in frames]
@@ -216,6 +237,8 @@ def main(argv=None):
                     entry["stage_grids"] = grids
                     entry["ms"] = round(ms_g, 5)
             set_shape(ctx, {**DEFAULT, "stage_grids": {}})
+            if "in_flight" in previous.get(key, {}):
+                entry["in_flight"] = previous[key]["in_flight"]
             classes[key] = entry
     ctx.close()
     with open(args.out, "w") as f:

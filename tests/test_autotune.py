@@ -41,8 +41,28 @@ def test_committed_table_holds_supported_shapes():
         from paper_2005_02704_amd.lidarseg import STAGES
         for stage, g in entry.get("stage_grids", {}).items():
             assert stage in STAGES and g in autotune.STAGE_GRIDS, (key, stage, g)
-    # the benchmark batch has an entry
+        f = entry.get("in_flight")
+        if f:
+            assert (f["tile_cells"], f["tile_threads"]) in shapes, key
+            assert f["grid"] > 0 and f["batches"] >= 2
+            for stage, g in f.get("stage_grids", {}).items():
+                assert stage in STAGES and g > 0, (key, stage, g)
+    # the benchmark batch has an entry, and a shape for two batches in flight
     assert "H128-W4096-F64" in table
+    assert "in_flight" in table["H128-W4096-F64"]
+
+
+def test_lookup_in_flight():
+    geos = [_geo(16, 1800)]
+    key = autotune.batch_class(geos)
+    one = {"grid": 2048, "tile_cells": 512, "tile_threads": 256, "ms": 1.0, "default_ms": 1.0}
+    assert autotune.lookup_in_flight(geos, table={key: one}) == {**{k: one[k] for k in ("grid", "tile_cells",
+                                                                                          "tile_threads")},
+                                                                 "stage_grids": {}}
+    two = {**one, "in_flight": {"grid": 512, "tile_cells": 2048, "tile_threads": 512, "batches": 2,
+                                "stage_grids": {"geom": 768}}}
+    assert autotune.lookup_in_flight(geos, table={key: two}) == {"grid": 512, "tile_cells": 2048,
+                                                                 "tile_threads": 512, "stage_grids": {"geom": 768}}
 
 
 def test_candidates_cover_every_shape_and_grid():
