@@ -183,3 +183,47 @@ def test_benchmark_batch_in_its_launch_configuration(ctx):
             assert sandwich(got[k]["labels"], frames[k].xyz, frames[k].sensor, 1), k
     finally:
         autotune.set_shape(ctx, {**autotune.DEFAULT, "stage_grids": {}})
+
+
+def test_benchmark_batch_two_in_flight_at_their_shape(ctx):
+    """The configuration the headline figure is timed in: the benchmark batch
+    on two contexts at once, each on its own stream, at the class's in-flight
+    launch shape, calls alternating.  Every call's outputs equal (bit for bit)
+    one batched call at the library's default shape, and sampled frames match
+    the oracle's geometry and lie between its thr -/+ 1e-4 partitions."""
+    import torch
+    import paper_2005_02704_amd as lp
+    from paper_2005_02704_amd import autotune
+    from gpu_helpers import THR, geometry
+    frames = synth.batch_frames(64, 2024)
+    ref = run_gpu(ctx, [(f.xyz, f.sensor, 1, 1, None) for f in frames], launch="batched")
+    geos = [geometry(f.sensor) for f in frames]
+    shape = autotune.lookup_in_flight(geos)
+    print(f"two in flight at {shape}", flush=True)
+    dev = torch.device("cuda", 0)
+    params = lp.make_params(1.0, 60.0, THR)
+    inputs = [(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)]
+    lanes = []
+    try:
+        for _ in range(2):
+            c = lp.LidarContext(0)
+            autotune.set_shape(c, shape)
+            outs = [lp.Outputs(g, dev) for g in geos]
+            lanes.append((c, c.prepare(inputs, params, outs), torch.cuda.Stream(dev), outs))
+        torch.cuda.synchronize()   # the outputs' fills are done before the lanes' streams use them
+        for k in range(6):
+            c, prep, st, _ = lanes[k % 2]
+            c.lidar_mesh_segment(prep, st, "batched")
+        torch.cuda.synchronize()
+        for _, _, _, outs in lanes:
+            for n, (o, r) in enumerate(zip(outs, ref)):
+                t = o.trimmed()
+                assert t["counts"] == r["counts"], n
+                for key in ("vertices", "normals", "labels", "triangles", "vertex_point"):
+                    assert np.array_equal(t[key].cpu().numpy(), r[key]), (n, key)
+    finally:
+        for c, _, _, _ in lanes:
+            c.close()
+    for k in (0, 31, 63):
+        check_geometry(ref[k], run_oracle(frames[k].xyz, frames[k].sensor, 1))
+        assert sandwich(ref[k]["labels"], frames[k].xyz, frames[k].sensor, 1), k
