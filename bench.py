@@ -112,8 +112,8 @@ def served_run(args, lp, synth, torch):
              for k in range(n_pool)] for q, (s, _) in enumerate(sensors)]
     geos = [lp.SensorGeometry(s.elevations(), s.n_azimuth, 1, 1, s.az0) for s, _ in sensors]
     pinned = [[torch.from_numpy(f.xyz).pin_memory() for f in row] for row in pool]
-    budget = 2 << 30
-    n_slots, max_batch = 4, 32
+    budget = 1 << 30
+    n_slots, max_batch = 4, 24
 
     def replay(srv, sched):
         lat, st, gs, wall = srv.replay([t for t, _, _ in sched], [q for _, q, _ in sched],
