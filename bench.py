@@ -274,6 +274,17 @@ CONFIGS = (("C1", "c1_16x1800", 1), ("C2", "c2_64x2048", 1), ("C2", "c2_64x2048"
            ("C2", "c2_64x2048", 4), ("C4", "c4_128x4096", 2))
 
 
+def _same_outputs(a, b):
+    """Two calls' outputs of one frame are equal: counts, and the vertices,
+    normals, labels, vertex points and triangles they cover (the buffers are
+    allocated at capacity; what lies past the counts is never written)."""
+    import torch
+    x, y = a.trimmed(), b.trimmed()
+    if x["counts"] != y["counts"]:
+        return False
+    return all(torch.equal(x[k], y[k]) for k in ("vertices", "normals", "labels", "vertex_point", "triangles"))
+
+
 def path_bytes(N, V, T):
     """Algorithmic bytes of the whole path: xyz of every input point in; vertices,
     normals, labels, vertex_point and triangles out."""
@@ -394,6 +405,7 @@ def main():
                     help="length of the served run (8 sensors, 10-20 Hz Poisson); 0 = skip")
     ap.add_argument("--in-flight", type=int, default=2,
                     help="also time the batched form with this many batches in flight (1 = skip)")
+    ap.add_argument("--in-flight-launch", default="batched", help="launch forms timed in flight (batched, graph)")
     ap.add_argument("--in-flight-shape", default="",
                     help='launch shape of the batches in flight, as JSON ({"grid": G, "tile_cells": C, '
                          '"tile_threads": T, "stage_grids": {stage: G}}); default: the autotuned table')
@@ -506,27 +518,28 @@ def main():
         # whole call over the batch, on one of `in_flight` contexts (workspace and
         # outputs of its own) and streams, taken in turn, so one batch's
         # latency-bound labelling stages overlap the next batch's mesh stages
-        name = f"batched_x{n_flight}"
-        log(f"timing batched launches, {n_flight} batches in flight, launch shape {if_shape}")
-        extra = []
-        for _ in range(n_flight):
-            c2 = lp.LidarContext(0)
-            from paper_2005_02704_amd import autotune
-            autotune.set_shape(c2, if_shape)
-            o2 = [lp.Outputs(g, dev) for g in geos]
-            extra.append((c2, c2.prepare(inputs, params, o2), torch.cuda.Stream(dev), o2))
-        torch.cuda.synchronize()   # the new outputs' fills are done before the lanes' streams use them
-        ms = run("batched", args.steps, args.warmup, [(c2, p2, s2) for c2, p2, s2, _ in extra], name)
-        same = all(torch.equal(a.labels, b.labels) and torch.equal(a.counts, b.counts)
-                   for c2, p2, s2, o2 in extra for a, b in zip(outs, o2))
-        log(f"  {name}: {ms:.3f} ms/step (host enqueue {host_ms[name]:.3f} ms/step), outputs as one in flight: {same}")
-        if not same:
-            raise RuntimeError("batches in flight gave other outputs than one batch alone")
-        forms[name] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-                       "launch_shape": if_shape}
-        for c2, _, _, _ in extra:
-            c2.close()
-        del extra
+        for launch in args.in_flight_launch.split(","):
+            name = f"{launch}_x{n_flight}"
+            log(f"timing {launch} launches, {n_flight} batches in flight, launch shape {if_shape}")
+            extra = []
+            for _ in range(n_flight):
+                c2 = lp.LidarContext(0)
+                from paper_2005_02704_amd import autotune
+                autotune.set_shape(c2, if_shape)
+                o2 = [lp.Outputs(g, dev) for g in geos]
+                extra.append((c2, c2.prepare(inputs, params, o2), torch.cuda.Stream(dev), o2))
+            torch.cuda.synchronize()   # the new outputs' fills are done before the lanes' streams use them
+            ms = run(launch, args.steps, args.warmup, [(c2, p2, s2) for c2, p2, s2, _ in extra], name)
+            same = all(_same_outputs(a, b) for c2, p2, s2, o2 in extra for a, b in zip(outs, o2))
+            log(f"  {name}: {ms:.3f} ms/step (host enqueue {host_ms[name]:.3f} ms/step), "
+                f"outputs as one in flight: {same}")
+            if not same:
+                raise RuntimeError("batches in flight gave other outputs than one batch alone")
+            forms[name] = {"points_per_s": round(N / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                           "launch_shape": if_shape}
+            for c2, _, _, _ in extra:
+                c2.close()
+            del extra
     # roofline kernel: per-stage HIP events on the launch stream over K batched steps.
     # k_geom moves most of the path's algorithmic bytes (the kept points in; the
     # vertices, normals, vertex points and triangles out), so the roofline is its.
