@@ -173,7 +173,7 @@ def served_run(args, lp, synth, torch):
             "capacity_plain_one_sweep_per_call_points_per_s": plain_st["points_per_s"],
             "pcie_link": link,
             "max_slots_in_flight": stats["max_slots_busy"], "peak_admitted_bytes": stats["peak_bytes"],
-            "server_device_bytes": stats["device_bytes"]}
+            "server_device_bytes": stats["device_bytes"]}, [f for row in pool for f in row]
 
 
 def mean_scores(outs, lp):
@@ -285,20 +285,26 @@ def _same_outputs(a, b):
     return all(torch.equal(x[k], y[k]) for k in ("vertices", "normals", "labels", "vertex_point", "triangles"))
 
 
+def _timed(fn):
+    t = time.perf_counter()
+    fn()
+    return time.perf_counter() - t
+
+
 def path_bytes(N, V, T):
     """Algorithmic bytes of the whole path: xyz of every input point in; vertices,
     normals, labels, vertex_point and triangles out."""
     return 12 * N + 12 * V + 12 * V + 4 * V + 4 * V + 12 * T
 
 
-def config_legs(lp, synth, torch, reps=200, lat_reps=100, oracle_runs=2, use_oracle=True):
+def config_legs(lp, synth, torch, reps=200, lat_reps=100):
     """Each single-sweep configuration on its own, one sweep per call, inputs
     resident in HBM, in the plain form (one kernel chain) and as a graph replay:
     points/s of calls enqueued back to back (host clock), the GPU time of each
     call (HIP events on the launch stream, p50/p99), the latency of one call at a
-    time (host call until its stream has finished, p50/p99), the algorithmic
-    bytes over the GPU time as a fraction of the HBM peak, and the oracle's
-    points/s on one host thread for the same sweep."""
+    time (host call until its stream has finished, p50/p99) and the algorithmic
+    bytes over the GPU time as a fraction of the HBM peak.  (The oracle's rate
+    on the same sweeps is timed in the CPU-baseline leg.)"""
     import numpy as np
     from paper_2005_02704_amd import autotune
     dev = torch.device("cuda", 0)
@@ -346,15 +352,6 @@ def config_legs(lp, synth, torch, reps=200, lat_reps=100, oracle_runs=2, use_ora
                            "algorithmic_gbs": round(alg / (gpu_mean * 1e-3) / 1e9, 1),
                            "frac_of_hbm_peak": round(alg / (gpu_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             row.update(vertices=V, triangles=T, segments=K, algorithmic_bytes=alg)
-        if use_oracle:
-            import oracle
-            best = None
-            for _ in range(oracle_runs):
-                t = time.perf_counter()
-                oracle.mesh_segment_frame(f, s=s)
-                el = time.perf_counter() - t
-                best = el if best is None else min(best, el)
-            row["oracle_1_thread_points_per_s"] = round(N / best, 1)
         ctx.close()
         res[key] = row
         log(f"  {key}: plain {row['plain']['points_per_s']:.3e} points/s (GPU p50 {row['plain']['gpu_ms_p50']:.4f} ms, "
@@ -584,7 +581,7 @@ def main():
     configs = None
     if not args.no_configs:
         log("single-sweep configurations")
-        configs = config_legs(lp, synth, torch, use_oracle=not args.no_cpu_baseline)
+        configs = config_legs(lp, synth, torch)
 
     accuracy = paper_timing = None
     if not args.no_accuracy:
@@ -593,9 +590,9 @@ def main():
         log("the paper's sweep shape")
         paper_timing = paper_shape_timing(lp, synth, torch, ctx, stream)
 
-    served = None
+    served = served_pool = None
     if args.served_seconds > 0:
-        served = served_run(args, lp, synth, torch)
+        served, served_pool = served_run(args, lp, synth, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -632,6 +629,21 @@ def main():
                "single_thread_points_per_s": round(rate_1, 1),
                "single_thread_sample": f"first {n_1} of the {args.frames} sweeps ({done_1} points)"}
         log(f"  oracle: {rate_n:.0f} points/s on {threads} threads, {rate_1:.0f} points/s on one")
+        if configs is not None:
+            # each single-sweep configuration on one thread (best of two runs)
+            per = {}
+            for cname, wname, s_ in CONFIGS:
+                f = synth.workload_frames(wname)[0]
+                best_t = min(_timed(lambda: oracle.mesh_segment_frame(f, s=s_)) for _ in range(2))
+                per[f"{cname}_{f.sensor.n_rings}x{f.sensor.n_azimuth}_s{s_}"] = round(f.n_points / best_t, 1)
+            cpu["per_config_1_thread_points_per_s"] = per
+        if served_pool is not None:
+            # the served pool's sweeps one at a time on one thread: the latency a
+            # host-only server would add per sweep, beside the served p50/p99
+            ms = np.array([_timed(lambda: oracle.mesh_segment_frame(f)) * 1e3 for f in served_pool])
+            cpu["served_pool_sweep_ms"] = {"p50": round(float(np.percentile(ms, 50)), 3),
+                                           "p99": round(float(np.percentile(ms, 99)), 3),
+                                           "sweeps": len(served_pool)}
 
     value = N / (ms_best * 1e-3)
     out = {
