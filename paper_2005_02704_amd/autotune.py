@@ -18,9 +18,9 @@ favour big tiles, many narrow ones more workgroups.  This module
 A class may also carry an "in_flight" shape, used when several batches of it
 run at once on their own contexts and streams: there each stage shares the GPU
 with the other batch's stages, and fewer workgroups per stage overlap better.
-Those entries are measured one shape per process with
-`bench.py --in-flight-shape` (the tuner here times one context only) and are
-kept when the table is rebuilt.
+`python -m paper_2005_02704_amd.autotune --in-flight 2` tunes it for the
+benchmark batch (fresh contexts for every candidate, shaped before any call and
+synchronised before the next); a rebuild of the table keeps it.
 
 Run `python -m paper_2005_02704_amd.autotune` on the GPU to rebuild the table
 for the standard synthetic workloads.
@@ -182,6 +182,75 @@ def tune(ctx, prepared, stream, launch="graph", log=None):
     return best[0], results
 
 
+def time_in_flight(inputs, geometries, params, shape, n_flight=2, steps=100, warm=6) -> float:
+    """Milliseconds per batch with `n_flight` batches in flight at `shape`: that
+    many fresh contexts, each with its own outputs and stream, take batched calls
+    in turn (host clock over `steps` calls, fully synchronised before and after).
+    The contexts are made, shaped and synchronised before any call, and closed
+    after the last; nothing is re-shaped while another context runs."""
+    import time
+    import torch
+    from . import lidarseg as lp
+    dev = torch.device("cuda", 0)
+    lanes = []
+    try:
+        for _ in range(n_flight):
+            c = lp.LidarContext(0)
+            set_shape(c, shape)
+            outs = [lp.Outputs(g, dev) for g in geometries]
+            lanes.append((c, c.prepare(inputs, params, outs), torch.cuda.Stream(dev), outs))
+        torch.cuda.synchronize()   # the outputs' fills are done before the lanes' streams use them
+        for k in range(warm):
+            c, p, st, _ = lanes[k % n_flight]
+            c.lidar_mesh_segment(p, st, "batched")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(steps):
+            c, p, st, _ = lanes[k % n_flight]
+            c.lidar_mesh_segment(p, st, "batched")
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / steps
+    finally:
+        torch.cuda.synchronize()
+        for c, _, _, _ in lanes:
+            c.close()
+
+
+IN_FLIGHT_GRIDS = (384, 512, 640, 768, 1024, 1536)
+IN_FLIGHT_STAGE_GRIDS = {"geom": (768, 1024, 1536, 3072), "cc": (768, 1536), "bin": (768, 1536)}
+
+
+def tune_in_flight(inputs, geometries, params, base_shape, n_flight=2, log=None):
+    """Shape for `n_flight` batches in flight, by coordinate descent from the
+    one-batch shape's tile: the grid first, then each stage of
+    IN_FLIGHT_STAGE_GRIDS in turn, a change kept only when it is 0.5 % faster
+    (each shape timed three times, the fastest kept).
+    Returns (shape, ms, ms of the one-batch shape in flight)."""
+    def run(shape):
+        ms = min(time_in_flight(inputs, geometries, params, shape, n_flight) for _ in range(3))
+        if log:
+            log(f"  in flight x{n_flight}: {shape} {ms:.4f} ms")
+        return ms
+
+    base_ms = run(base_shape)
+    tile = {"tile_cells": base_shape["tile_cells"], "tile_threads": base_shape["tile_threads"]}
+    best, best_ms = None, None
+    for g in IN_FLIGHT_GRIDS:
+        shape = {"grid": g, **tile, "stage_grids": {}}
+        ms = run(shape)
+        if best_ms is None or ms < best_ms:
+            best, best_ms = shape, ms
+    for stage, grids in IN_FLIGHT_STAGE_GRIDS.items():
+        for g in grids:
+            shape = {**best, "stage_grids": {**best["stage_grids"], stage: g}}
+            ms = run(shape)
+            if ms < best_ms * 0.995:
+                best, best_ms = shape, ms
+    if base_ms <= best_ms:
+        return base_shape, base_ms, base_ms
+    return best, best_ms, base_ms
+
+
 def _workloads():
     """The batches the table is built for: the benchmark batch, served-style
     groups of a few sensors, and the single-frame workloads."""
@@ -197,6 +266,8 @@ def _workloads():
 def main(argv=None):
     ap = argparse.ArgumentParser(description="rebuild the launch-shape table on the GPU")
     ap.add_argument("--out", default=TABLE_PATH)
+    ap.add_argument("--in-flight", type=int, default=0, metavar="N",
+                    help="only (re)tune the benchmark batch's shape for N batches in flight, keeping the rest")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
@@ -208,8 +279,25 @@ def main(argv=None):
 
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
-    ctx = lp.LidarContext(0)
     params = lp.make_params(1.0, 60.0, (0.2, 0.2, 0.2))
+    if args.in_flight > 1:
+        classes = load_table(args.out)
+        frames = synth.batch_frames(64, 2024)
+        geos = [lp.SensorGeometry(f.sensor.elevations(), f.sensor.n_azimuth, 1, 1, f.sensor.az0) for f in frames]
+        key = batch_class(geos)
+        if key not in classes:
+            raise SystemExit(f"no one-batch entry for {key}: tune the table first")
+        inputs = [(torch.from_numpy(f.xyz).to(dev), g, None) for f, g in zip(frames, geos)]
+        one = lookup(geos, classes)
+        shape, ms, base_ms = tune_in_flight(inputs, geos, params, one, args.in_flight, log)
+        classes[key]["in_flight"] = {**shape, "batches": args.in_flight, "ms": round(ms, 5),
+                                     "one_batch_shape_ms": round(base_ms, 5)}
+        log(f"{key}: in flight x{args.in_flight} {shape} {ms:.4f} ms (one-batch shape {base_ms:.4f} ms)")
+        with open(args.out, "w") as f:
+            json.dump({"device": torch.cuda.get_device_name(0), "classes": classes}, f, indent=1, sort_keys=True)
+        log(f"wrote {args.out}")
+        return
+    ctx = lp.LidarContext(0)
     classes = {}
     previous = load_table(args.out)
     for name, frames in _workloads():
