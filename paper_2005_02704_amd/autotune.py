@@ -220,14 +220,17 @@ IN_FLIGHT_GRIDS = (384, 512, 640, 768, 1024, 1536)
 IN_FLIGHT_STAGE_GRIDS = {"geom": (768, 1024, 1536, 3072), "cc": (768, 1536), "bin": (768, 1536)}
 
 
-def tune_in_flight(inputs, geometries, params, base_shape, n_flight=2, log=None):
+def tune_in_flight(inputs, geometries, params, base_shape, n_flight=2, log=None, timer=None):
     """Shape for `n_flight` batches in flight, by coordinate descent from the
     one-batch shape's tile: the grid first, then each stage of
     IN_FLIGHT_STAGE_GRIDS in turn, a change kept only when it is 0.5 % faster
-    (each shape timed three times, the fastest kept).
+    (each shape timed three times, the fastest kept).  timer(shape) -> ms
+    replaces time_in_flight (for tests).
     Returns (shape, ms, ms of the one-batch shape in flight)."""
+    timer = timer or (lambda shape: time_in_flight(inputs, geometries, params, shape, n_flight))
+
     def run(shape):
-        ms = min(time_in_flight(inputs, geometries, params, shape, n_flight) for _ in range(3))
+        ms = min(timer(shape) for _ in range(3))
         if log:
             log(f"  in flight x{n_flight}: {shape} {ms:.4f} ms")
         return ms

@@ -69,3 +69,27 @@ def test_candidates_cover_every_shape_and_grid():
     c = autotune.candidates()
     assert len(c) == len(autotune.TILE_SHAPES) * len(autotune.GRIDS)
     assert len({tuple(sorted(x.items())) for x in c}) == len(c)
+
+
+def test_in_flight_descent_picks_the_fastest_and_keeps_only_real_gains():
+    """The in-flight tuner's coordinate descent on a made-up cost: the grid is
+    chosen first, then a stage count that is more than 0.5 % faster is kept, and
+    one that is faster by less is not; the one-batch shape wins when nothing
+    beats it."""
+    base = {"grid": 1536, "tile_cells": 2048, "tile_threads": 512, "stage_grids": {"geom": 3072}}
+
+    def cost(shape):
+        g = shape["grid"]
+        ms = 0.40 + abs(g - 512) * 1e-5
+        sg = shape["stage_grids"]
+        if sg.get("geom") == 768:
+            ms -= 0.01          # a real gain
+        if sg.get("cc") == 1536:
+            ms -= 0.0005        # below the 0.5 % bar
+        return ms
+
+    shape, ms, base_ms = autotune.tune_in_flight(None, None, None, base, timer=cost)
+    assert shape == {"grid": 512, "tile_cells": 2048, "tile_threads": 512, "stage_grids": {"geom": 768}}
+    assert abs(ms - 0.39) < 1e-9 and abs(base_ms - cost(base)) < 1e-12
+    shape, ms, base_ms = autotune.tune_in_flight(None, None, None, base, timer=lambda s: 0.3 if s is base else 0.5)
+    assert shape is base and ms == base_ms == 0.3
