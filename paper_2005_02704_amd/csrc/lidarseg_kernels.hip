@@ -67,6 +67,11 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// Outputs that no later stage reads (vertices, vertex points, triangles,
+// labels, point labels) are written with non-temporal stores, so they do not
+// displace what the next stages read back (the normals, the forest) from the
+// caches.  The normals stay ordinary stores: k_cc reads them.
+
 __device__ __forceinline__ const FrameDesc* frames_of(const BatchHeader* h) {
     return reinterpret_cast<const FrameDesc*>(h + 1);
 }
@@ -738,10 +743,10 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
             if (l < nown) {
                 const float4 p = sc[lx];
                 const auto vo = gmem(fd->vertices) + 3 * (int64_t)vid[r];
-                vo[0] = p.x;
-                vo[1] = p.y;
-                vo[2] = p.z;
-                if (fd->vpoint) gmem(fd->vpoint)[vid[r]] = saux[l];
+                __builtin_nontemporal_store(p.x, &vo[0]);
+                __builtin_nontemporal_store(p.y, &vo[1]);
+                __builtin_nontemporal_store(p.z, &vo[2]);
+                if (fd->vpoint) __builtin_nontemporal_store(saux[l], &gmem(fd->vpoint)[vid[r]]);
                 if (fd->scores) ws.vtruth[fd->cell_off + vid[r]] = gmem(fd->truth)[saux[l]];
                 saux[l] = ltr[r];
             }
@@ -767,12 +772,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
                     int ti = saux[l];
                     if (a >= 0 && b >= 0) {
                         const auto to = gmem(fd->tris) + 3 * (int64_t)ti;
-                        to[0] = v; to[1] = a; to[2] = b;
+                        __builtin_nontemporal_store(v, &to[0]); __builtin_nontemporal_store(a, &to[1]); __builtin_nontemporal_store(b, &to[2]);
                         ++ti;
                     }
                     if (b >= 0 && c >= 0) {
                         const auto to = gmem(fd->tris) + 3 * (int64_t)ti;
-                        to[0] = v; to[1] = b; to[2] = c;
+                        __builtin_nontemporal_store(v, &to[0]); __builtin_nontemporal_store(b, &to[1]); __builtin_nontemporal_store(c, &to[2]);
                     }
                 }
                 float nx_, ny_, nz_;
@@ -1386,7 +1391,7 @@ __global__ __launch_bounds__(NT) void k_resolve(const BatchHeader* __restrict__ 
                 const int root = cur[r] - base;
                 const uint64_t below = rbits[r] & ((1ull << (root & 63)) - 1ull);
                 lab = 1 + rbase[r] + (int)rpre[r] + __popcll(below);
-                gmem(fd->labels)[v] = lab;
+                __builtin_nontemporal_store(lab, &gmem(fd->labels)[v]);
             }
             if (fd->min_seg > 1) {
                 // segment sizes: one atomic per distinct label of the wave
@@ -1468,7 +1473,9 @@ __global__ __launch_bounds__(NT) void k_post(const BatchHeader* __restrict__ hdr
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
                 const int64_t p = p0 + r * NT;
-                if (p < fd->n_points) gmem(fd->point_labels)[p] = backfill_label(fd, ws, ws.pcell[fd->pt_off + p]);
+                if (p < fd->n_points)
+                    __builtin_nontemporal_store(backfill_label(fd, ws, ws.pcell[fd->pt_off + p]),
+                                                &gmem(fd->point_labels)[p]);
             }
         }
     }
