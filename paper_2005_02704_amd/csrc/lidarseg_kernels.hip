@@ -67,10 +67,12 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
     return (__attribute__((address_space(1))) T*)p;
 }
 
-// Outputs that no later stage reads (vertices, vertex points, triangles,
-// labels, point labels) are written with non-temporal stores, so they do not
-// displace what the next stages read back (the normals, the forest) from the
-// caches.  The normals stay ordinary stores: k_cc reads them.
+// Dense outputs that no later stage reads (vertices, vertex points, labels,
+// point labels) are written with non-temporal stores, so they do not displace
+// what the next stages read back (the normals, the forest) from the caches.
+// The normals stay ordinary stores (k_cc reads them), and so do the
+// triangles: a lane writes one only where the triangle exists, and streamed
+// partial lines would cost whole-line writes.
 
 __device__ __forceinline__ const FrameDesc* frames_of(const BatchHeader* h) {
     return reinterpret_cast<const FrameDesc*>(h + 1);
@@ -772,12 +774,12 @@ __global__ __launch_bounds__(NT, (MAXC / NT <= 4 ? 6 : 1)) void k_geom(const Bat
                     int ti = saux[l];
                     if (a >= 0 && b >= 0) {
                         const auto to = gmem(fd->tris) + 3 * (int64_t)ti;
-                        __builtin_nontemporal_store(v, &to[0]); __builtin_nontemporal_store(a, &to[1]); __builtin_nontemporal_store(b, &to[2]);
+                        to[0] = v; to[1] = a; to[2] = b;
                         ++ti;
                     }
                     if (b >= 0 && c >= 0) {
                         const auto to = gmem(fd->tris) + 3 * (int64_t)ti;
-                        __builtin_nontemporal_store(v, &to[0]); __builtin_nontemporal_store(b, &to[1]); __builtin_nontemporal_store(c, &to[2]);
+                        to[0] = v; to[1] = b; to[2] = c;
                     }
                 }
                 float nx_, ny_, nz_;
